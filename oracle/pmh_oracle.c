@@ -1,0 +1,759 @@
+/*
+ * pmh_oracle.c -- plain, sequential CPU oracle for ProbMinHash signatures.
+ *
+ *   O. Ertl, "ProbMinHash -- A Class of Locality-Sensitive Hash Algorithms for
+ *   the (Probability) Jaccard Similarity", IEEE TKDE 2020 (arXiv 1911.00675).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the GPU library: every primitive
+ * below is written here from its definition.
+ *
+ * What it computes (all arithmetic IEEE binary64, round-to-nearest, no
+ * contraction; fma only where written):
+ *
+ *   * the per-element random streams of the four ProbMinHash variants
+ *     (Sec. 2.1 "Sequence Generation", Sec. 2.3-2.6), driven by a counter-based
+ *     SplitMix64 word stream, an atanh-series logarithm and Lemire's bounded
+ *     integers (the readings of Sec. 3's PRNG remarks listed in the design
+ *     notes);
+ *   * the truncated-exponential sampler of Sec. 2.8 (algorithm "Fast
+ *     generation of random values from Exp(lambda;0,1)");
+ *   * the sequential algorithms ProbMinHash1-4 (Sec. 2.3-2.6) with the
+ *     binary-tree stop-limit maintenance of Sec. 2.2 and the lazy Fisher-Yates
+ *     generator of Sec. 2.4, transcribed into a 64-bit (value, position) key
+ *     space;
+ *   * the interleaved variants ProbMinHash1a and ProbMinHash3a (Sec. 2.7);
+ *   * a brute-force reference that generates every point of every element's
+ *     stream with no stop rule and takes the per-label minimum, i.e. the
+ *     signature definition of eq. (1) with the hash values of eq. (9).
+ *
+ * Pins (see tests/): sequential == brute force == interleaved on tiny inputs;
+ * logarithm/expm1/log1p against the C library within a few ulp; Exp(1),
+ * truncated-exponential, Lemire and Fisher-Yates distribution tests; the
+ * collision law Pr(z_k(A) = z_k(B)) = J_P; the relative-MSE band of Sec. 3.1;
+ * SuperMinHash's alpha(m,u) for ProbMinHash4 with equal weights (Sec. 2.9).
+ * parity unpinned: the exact bit pattern of the word stream (SplitMix64 output
+ * function applied to K + (c+1)*phi) has no published test vector available
+ * offline; it is pinned only by its stated definition and by the statistical
+ * tests above.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O_PHI 0x9E3779B97F4A7C15ULL
+#define O_EMPTY 0xFFFFFFFFFFFFFFFFULL
+#define O_POS_MASK 0xFFFFFULL /* 20 position bits */
+#define O_MAX_SET ((uint64_t)1 << 20)
+#define O_MAX_M 16384u
+
+enum { O_OK = 0, O_ERR_ARG = 1, O_ERR_M_RANGE = 2, O_ERR_VARIANT_M = 3, O_ERR_WEIGHT = 4,
+       O_ERR_SET_TOO_LARGE = 5, O_ERR_OOM = 7 };
+
+/* ------------------------------------------------------------------------ */
+/* Randomness: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) addressed by a
+ * counter.  The element key K is a hash of (seed, element id) only, so equal
+ * elements of different sets draw identical streams (Sec. 2, "PRNG seeded with
+ * a hash of d").  Word c of element K is the c-th SplitMix64 output for the
+ * state K: mix(K + (c+1)*phi).  c = (i << 8) | t addresses slot t of point i. */
+static inline uint64_t o_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+static inline uint64_t o_word(uint64_t K, uint64_t i, unsigned t) {
+    uint64_t c = (i << 8) | (uint64_t)t;
+    return o_mix64(K + (c + 1) * O_PHI);
+}
+/* slots of point i */
+#define O_SLOT_VALUE 0u   /* uniform behind the point value */
+#define O_SLOT_LABEL 1u   /* label draw; Lemire redraws use 2..9 */
+#define O_SLOT_REJ 16u    /* truncated-exponential rejection pairs use 16..79 */
+
+static inline double o_u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }        /* [0,1) */
+static inline double o_upos(uint64_t w) { return (double)((w >> 11) + 1) * 0x1p-53; } /* (0,1] */
+
+/* ------------------------------------------------------------------------ */
+/* Logarithm written from ln x = e ln 2 + 2 atanh((f-1)/(f+1)), x = 2^e f with
+ * f in [sqrt(1/2), sqrt(2)); atanh(s) = s + s^3/3 + s^5/5 + ...  For |s| <=
+ * 0.1716 the series terms up to s^21 reach below 2^-53 relative. */
+static const double O_LN2_HI = 0x1.62e42fefa0000p-1; /* ln 2 rounded to 36 bits */
+static const double O_LN2_LO = 0x1.cf79abc9e3b3ap-40; /* ln 2 - O_LN2_HI */
+
+double or_log(double x) {
+    uint64_t b;
+    memcpy(&b, &x, 8);
+    int e = (int)((b >> 52) & 0x7FF) - 1023;
+    uint64_t mant = b & 0xFFFFFFFFFFFFFULL;
+    uint64_t fb;
+    if (mant >= 0x6A09E667F3BCDULL) { /* f >= sqrt(2): use f/2 */
+        fb = mant | (1022ULL << 52);
+        e += 1;
+    } else {
+        fb = mant | (1023ULL << 52);
+    }
+    double f;
+    memcpy(&f, &fb, 8);
+    double s = (f - 1.0) / (f + 1.0);
+    double t = s * s;
+    /* Q(t) = sum_{j=1..10} (2/(2j+1)) t^(j-1) */
+    double q = 2.0 / 21.0;
+    q = fma(q, t, 2.0 / 19.0);
+    q = fma(q, t, 2.0 / 17.0);
+    q = fma(q, t, 2.0 / 15.0);
+    q = fma(q, t, 2.0 / 13.0);
+    q = fma(q, t, 2.0 / 11.0);
+    q = fma(q, t, 2.0 / 9.0);
+    q = fma(q, t, 2.0 / 7.0);
+    q = fma(q, t, 2.0 / 5.0);
+    q = fma(q, t, 2.0 / 3.0);
+    double lf = 2.0 * s + (s * t) * q;
+    double de = (double)e;
+    return de * O_LN2_HI + (de * O_LN2_LO + lf);
+}
+
+/* log(1+u) for u > 0; used only for the per-m constants. */
+double or_log1p(double u) {
+    if (u > 1.0) return or_log(1.0 + u);
+    double s = u / (2.0 + u); /* log1p(u) = 2 atanh(u/(2+u)), |s| <= 1/3 */
+    double t = s * s;
+    double q = 2.0 / 49.0; /* j = 24 */
+    for (int j = 23; j >= 1; --j) q = fma(q, t, 2.0 / (double)(2 * j + 1));
+    return 2.0 * s + (s * t) * q;
+}
+
+/* exp(t) - 1 for t in [0, ln 2]: Taylor series to degree 18, coefficients
+ * e_k = e_{k-1} / k, e_0 = 1, evaluated by Horner with fma. */
+double or_expm1(double t) {
+    double e[19];
+    e[0] = 1.0;
+    for (int k = 1; k <= 18; ++k) e[k] = e[k - 1] / (double)k;
+    double p = e[18];
+    for (int k = 17; k >= 1; --k) p = fma(p, t, e[k]);
+    return p * t;
+}
+
+/* Exp(1) by inversion; 0 - log(u) keeps the result +0 for u = 1. */
+static inline double o_exp1(uint64_t w) { return 0.0 - or_log(o_upos(w)); }
+
+/* Uniform integer in [0, s), Lemire's multiply-and-reject method on the high
+ * 32 bits of the label words of point i (at most 8 redraws). */
+static uint32_t o_lemire(uint64_t K, uint64_t i, uint32_t s) {
+    uint64_t x = o_word(K, i, O_SLOT_LABEL) >> 32;
+    uint64_t prod = x * (uint64_t)s;
+    uint32_t lo = (uint32_t)prod;
+    if (lo < s) {
+        uint32_t thr = (uint32_t)(0u - s) % s;
+        for (unsigned r = 1; lo < thr && r <= 8; ++r) {
+            x = o_word(K, i, O_SLOT_LABEL + r) >> 32;
+            prod = x * (uint64_t)s;
+            lo = (uint32_t)prod;
+        }
+    }
+    return (uint32_t)(prod >> 32);
+}
+
+/* Truncated exponential Exp(lam; 0, 1) of Sec. 2.8 (area split into a
+ * rectangle under e^-lam, then rejection from a triangle via a half-height
+ * rectangle with reflection, two tangent tests and a final exact test).
+ * c1 = (e^lam - 1)/lam, c2 = log(2/(1+e^-lam))/lam, c3 = (1-e^-lam)/lam.
+ * The rejection loop is capped at 32 rounds (Sec. 3 recommends capped loops). */
+static double o_te(uint64_t K, uint64_t i, double lam, double c1, double c2, double c3) {
+    double x = c1 * o_u53(o_word(K, i, O_SLOT_VALUE));
+    if (x < 1.0) return x;
+    for (unsigned it = 0; it < 32; ++it) {
+        x = o_u53(o_word(K, i, O_SLOT_REJ + 2 * it));
+        if (x < c2) return x;
+        double y = 0.5 * o_u53(o_word(K, i, O_SLOT_REJ + 2 * it + 1));
+        if (y > 1.0 - x) {
+            x = 1.0 - x;
+            y = 1.0 - y;
+        }
+        if (x <= c3 * (1.0 - y)) return x;
+        double yc = y * c1;
+        if (yc <= 1.0 - x) return x;
+        if (yc * lam <= or_expm1(lam * (1.0 - x))) return x;
+    }
+    return x;
+}
+
+/* Packed key: sign, exponent and top 32 fraction bits of the point value,
+ * then the 20-bit position.  Integer order = (value truncated, position). */
+static inline uint64_t o_key(double x, uint32_t p) {
+    uint64_t b;
+    memcpy(&b, &x, 8);
+    return (b & ~O_POS_MASK) | (uint64_t)p;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-(variant, m) constants. */
+typedef struct {
+    int variant;
+    uint32_t m;
+    uint64_t imax;  /* stream length cap for sampling with replacement */
+    double *beta;   /* PMH2: beta[i] = m/(m-i+1), i = 1..m */
+    double lam3, c1, c2, c3;       /* PMH3 */
+    double *lam4, *c14, *c24, *c34; /* PMH4, i = 1..m-1 */
+    double *gam, *dgam;             /* PMH4: gamma[0..m-1], dgamma[1..m-1] */
+    double delta;                   /* PMH4 */
+} o_params;
+
+static unsigned o_bitlen(uint32_t m) {
+    unsigned b = 0;
+    while (m) { ++b; m >>= 1; }
+    return b;
+}
+
+uint64_t or_imax(uint32_t m) { return 6ULL * m * o_bitlen(m) + 64; }
+
+static void o_params_free(o_params *P) {
+    free(P->beta); free(P->lam4); free(P->c14); free(P->c24); free(P->c34);
+    free(P->gam); free(P->dgam);
+    memset(P, 0, sizeof(*P));
+}
+
+static int o_params_init(o_params *P, int variant, uint32_t m) {
+    memset(P, 0, sizeof(*P));
+    if (variant < 1 || variant > 4) return O_ERR_ARG;
+    if (m < 1 || m > O_MAX_M) return O_ERR_M_RANGE;
+    if ((variant == 3 || variant == 4) && m < 2) return O_ERR_VARIANT_M;
+    P->variant = variant;
+    P->m = m;
+    P->imax = or_imax(m);
+    double dm = (double)m;
+    if (variant == 2) {
+        P->beta = malloc(sizeof(double) * (m + 1));
+        if (!P->beta) return O_ERR_OOM;
+        P->beta[0] = 0.0;
+        for (uint32_t i = 1; i <= m; ++i) P->beta[i] = dm / (double)(m - i + 1);
+    } else if (variant == 3) {
+        /* lambda = log(1 + 1/(m-1)); since e^lambda = m/(m-1) the sampler
+         * constants have closed forms in 1/(m-1), 1/(2m-1), 1/m. */
+        double a = 1.0 / (double)(m - 1);
+        P->lam3 = or_log1p(a);
+        P->c1 = a / P->lam3;
+        P->c2 = or_log1p(1.0 / (double)(2 * m - 1)) / P->lam3;
+        P->c3 = (1.0 / dm) / P->lam3;
+    } else if (variant == 4) {
+        P->lam4 = malloc(sizeof(double) * m);
+        P->c14 = malloc(sizeof(double) * m);
+        P->c24 = malloc(sizeof(double) * m);
+        P->c34 = malloc(sizeof(double) * m);
+        P->gam = malloc(sizeof(double) * m);
+        P->dgam = malloc(sizeof(double) * m);
+        if (!P->lam4 || !P->c14 || !P->c24 || !P->c34 || !P->gam || !P->dgam) {
+            o_params_free(P);
+            return O_ERR_OOM;
+        }
+        P->lam4[0] = P->c14[0] = P->c24[0] = P->c34[0] = 0.0;
+        for (uint32_t i = 1; i < m; ++i) {
+            double a = 1.0 / (double)(m - i);
+            double l = or_log1p(a); /* lambda_i = log(1 + 1/(m-i)) */
+            P->lam4[i] = l;
+            P->c14[i] = a / l;
+            P->c24[i] = or_log1p(1.0 / (double)(2 * (m - i) + 1)) / l;
+            P->c34[i] = (1.0 / (double)(m - i + 1)) / l;
+        }
+        P->gam[0] = 0.0;
+        for (uint32_t i = 1; i < m; ++i)
+            P->gam[i] = or_log1p((double)i / (double)(m - i)) / P->lam4[1];
+        P->dgam[0] = 0.0;
+        for (uint32_t i = 1; i < m; ++i) P->dgam[i] = P->gam[i] - P->gam[i - 1];
+        P->delta = 1.0 / P->lam4[1];
+    }
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Point streams.  Point i >= 1 of element K (weight inverse winv).  PMH1/PMH2
+ * accumulate the exponential spacings in 64-bit fixed point (2^-32 units) and
+ * round once: x_i = winv * (T_i 2^-32), T_i = T_{i-1} + floor(s_i 2^32). */
+static inline uint64_t o_spacing(const o_params *P, uint64_t K, uint64_t i) {
+    double E = o_exp1(o_word(K, i, O_SLOT_VALUE));
+    if (P->variant == 2) E = P->beta[i] * E;
+    return (uint64_t)(E * 0x1p32);
+}
+static inline double o_fixed_value(double winv, uint64_t T) { return winv * ((double)T * 0x1p-32); }
+
+static inline double o_value3(const o_params *P, uint64_t K, uint64_t i, double winv) {
+    double lb = winv * (double)(i - 1);
+    return lb + winv * o_te(K, i, P->lam3, P->c1, P->c2, P->c3);
+}
+static inline double o_value4(const o_params *P, uint64_t K, uint64_t i, double winv) {
+    uint32_t m = P->m;
+    if (i < m)
+        return winv * (P->gam[i - 1] +
+                       P->dgam[i] * o_te(K, i, P->lam4[i], P->c14[i], P->c24[i], P->c34[i]));
+    return winv * (P->gam[m - 1] + P->delta * o_exp1(o_word(K, i, O_SLOT_VALUE)));
+}
+
+/* Lazy Fisher-Yates permutation generator of Sec. 2.4 (arrays g, v and the
+ * version counter c), 0-based positions.  Step i (1-based) draws
+ * j = (i-1) + U{0..m-i}, returns g[j], moves g[i-1] into slot j. */
+typedef struct {
+    uint32_t *g, *v;
+    uint32_t c, i, m;
+} o_perm;
+
+static int o_perm_init(o_perm *F, uint32_t m) {
+    F->g = malloc(sizeof(uint32_t) * m);
+    F->v = calloc(m, sizeof(uint32_t));
+    F->c = 0;
+    F->i = 0;
+    F->m = m;
+    return (F->g && F->v) ? O_OK : O_ERR_OOM;
+}
+static void o_perm_free(o_perm *F) { free(F->g); free(F->v); }
+static inline void o_perm_reset(o_perm *F) {
+    if (F->c == 0xFFFFFFFFu) { /* version counter wraps: forget old versions */
+        memset(F->v, 0, sizeof(uint32_t) * F->m);
+        F->c = 0;
+    }
+    F->i = 0;
+    F->c += 1;
+}
+static inline uint32_t o_perm_next(o_perm *F, uint64_t K) {
+    F->i += 1;
+    uint32_t i = F->i;
+    uint32_t j = (i - 1) + o_lemire(K, i, F->m - i + 1);
+    uint32_t k = (F->v[j] == F->c) ? F->g[j] : j;
+    F->g[j] = (F->v[i - 1] == F->c) ? F->g[i - 1] : (i - 1);
+    F->v[j] = F->c;
+    return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stop-limit tree of Sec. 2.2 over keys: q[1..m] leaves, q[m+1..2m-1] inner
+ * nodes, parent of k is m + ceil(k/2), root q[2m-1] = max_k q[k]. */
+static inline void o_tree_update(uint64_t *q, uint32_t m, uint32_t k1, uint64_t h) {
+    uint64_t k = k1; /* 1-based */
+    while (h < q[k]) {
+        q[k] = h;
+        uint64_t i = m + (k + 1) / 2;
+        if (i >= 2ULL * m) break;
+        uint64_t j = ((k - 1) ^ 1ULL) + 1;
+        if (q[j] >= q[i]) break;
+        if (h < q[j]) h = q[j];
+        k = i;
+    }
+}
+
+typedef struct {
+    uint64_t points; /* points generated */
+    uint64_t labels; /* labels drawn */
+} o_stats;
+
+static inline uint64_t o_elem_key(uint64_t seedhash, uint64_t id) { return o_mix64(id ^ seedhash); }
+
+/* Sequential ProbMinHash over one set.  q has 2m entries (index 0 unused). */
+static void o_sign_seq(const o_params *P, uint64_t seedhash, const uint64_t *ids, const double *w,
+                       uint32_t n, uint64_t *q, o_perm *F, o_stats *st) {
+    const uint32_t m = P->m;
+    const uint64_t root = 2ULL * m - 1;
+    for (uint64_t k = 1; k <= root; ++k) q[k] = O_EMPTY;
+    for (uint32_t p = 0; p < n; ++p) {
+        if (!(w[p] > 0.0)) continue;
+        const double winv = 1.0 / w[p];
+        const uint64_t K = o_elem_key(seedhash, ids[p]);
+        if (P->variant == 1) { /* ProbMinHash1, Sec. 2.3 */
+            uint64_t i = 1, T = o_spacing(P, K, 1);
+            double h = o_fixed_value(winv, T);
+            st->points++;
+            while (o_key(h, p) < q[root]) {
+                uint32_t k = o_lemire(K, i, m);
+                st->labels++;
+                uint64_t key = o_key(h, p);
+                if (key < q[k + 1]) {
+                    o_tree_update(q, m, k + 1, key);
+                    if (key >= q[root]) break;
+                }
+                if (i == P->imax) break;
+                ++i;
+                T += o_spacing(P, K, i);
+                h = o_fixed_value(winv, T);
+                st->points++;
+            }
+        } else if (P->variant == 2) { /* ProbMinHash2, Sec. 2.4 */
+            o_perm_reset(F);
+            uint64_t i = 1, T = o_spacing(P, K, 1);
+            double h = o_fixed_value(winv, T);
+            st->points++;
+            while (o_key(h, p) < q[root]) {
+                uint32_t k = o_perm_next(F, K);
+                st->labels++;
+                uint64_t key = o_key(h, p);
+                if (key < q[k + 1]) {
+                    o_tree_update(q, m, k + 1, key);
+                    if (key >= q[root]) break;
+                }
+                if (i == m) break; /* the permutation is exhausted */
+                ++i;
+                T += o_spacing(P, K, i);
+                h = o_fixed_value(winv, T);
+                st->points++;
+            }
+        } else if (P->variant == 3) { /* ProbMinHash3, Sec. 2.5 */
+            uint64_t i = 1;
+            double h = o_value3(P, K, 1, winv);
+            st->points++;
+            for (;;) {
+                uint64_t key = o_key(h, p);
+                if (key < q[root]) {
+                    uint32_t k = o_lemire(K, i, m);
+                    st->labels++;
+                    if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
+                }
+                if (i == P->imax) break;
+                ++i;
+                /* point i lies in [winv (i-1), winv i): stop on the lower bound */
+                if (o_key(winv * (double)(i - 1), p) >= q[root]) break;
+                h = o_value3(P, K, i, winv);
+                st->points++;
+            }
+        } else { /* ProbMinHash4, Sec. 2.6 */
+            o_perm_reset(F);
+            uint64_t i = 1;
+            double h = o_value4(P, K, 1, winv);
+            st->points++;
+            for (;;) {
+                /* every generated point takes its Fisher-Yates step so the
+                 * label of the next point is defined */
+                uint32_t k = o_perm_next(F, K);
+                st->labels++;
+                uint64_t key = o_key(h, p);
+                if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
+                if (i == m) break;
+                ++i;
+                if (o_key(winv * P->gam[i - 1], p) >= q[root]) break;
+                h = o_value4(P, K, i, winv);
+                st->points++;
+            }
+        }
+    }
+}
+
+/* Interleaved ProbMinHash1a / ProbMinHash3a of Sec. 2.7: first points of all
+ * elements in one pass, then repeated passes over a buffer of live elements. */
+typedef struct {
+    uint32_t p;
+    double winv;
+    uint64_t K;
+    uint64_t i; /* index of the last generated point */
+    uint64_t T; /* PMH1 fixed-point accumulator */
+    double h;
+} o_live;
+
+static int o_sign_interleaved(const o_params *P, uint64_t seedhash, const uint64_t *ids,
+                              const double *w, uint32_t n, uint64_t *q, o_stats *st) {
+    const uint32_t m = P->m;
+    const uint64_t root = 2ULL * m - 1;
+    for (uint64_t k = 1; k <= root; ++k) q[k] = O_EMPTY;
+    o_live *buf = malloc(sizeof(o_live) * (n ? n : 1));
+    if (!buf) return O_ERR_OOM;
+    uint32_t s = 0;
+    for (uint32_t p = 0; p < n; ++p) {
+        if (!(w[p] > 0.0)) continue;
+        double winv = 1.0 / w[p];
+        uint64_t K = o_elem_key(seedhash, ids[p]);
+        if (P->variant == 1) {
+            uint64_t T = o_spacing(P, K, 1);
+            double h = o_fixed_value(winv, T);
+            st->points++;
+            uint64_t key = o_key(h, p);
+            if (key >= q[root]) continue;
+            uint32_t k = o_lemire(K, 1, m);
+            st->labels++;
+            if (key < q[k + 1]) {
+                o_tree_update(q, m, k + 1, key);
+                if (key >= q[root]) continue;
+            }
+            if (P->imax == 1) continue;
+            buf[s++] = (o_live){p, winv, K, 1, T, h};
+        } else {
+            double h = o_value3(P, K, 1, winv);
+            st->points++;
+            uint64_t key = o_key(h, p);
+            if (key < q[root]) {
+                uint32_t k = o_lemire(K, 1, m);
+                st->labels++;
+                if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
+            }
+            if (o_key(winv, p) >= q[root] || P->imax == 1) continue;
+            buf[s++] = (o_live){p, winv, K, 1, 0, h};
+        }
+    }
+    while (s > 0) {
+        uint32_t t = 0;
+        for (uint32_t j = 0; j < s; ++j) {
+            o_live e = buf[j];
+            if (P->variant == 1) {
+                if (o_key(e.h, e.p) >= q[root]) continue;
+                e.i += 1;
+                e.T += o_spacing(P, e.K, e.i);
+                e.h = o_fixed_value(e.winv, e.T);
+                st->points++;
+                uint64_t key = o_key(e.h, e.p);
+                if (key >= q[root]) continue;
+                uint32_t k = o_lemire(e.K, e.i, m);
+                st->labels++;
+                if (key < q[k + 1]) {
+                    o_tree_update(q, m, k + 1, key);
+                    if (key >= q[root]) continue;
+                }
+                if (e.i == P->imax) continue;
+            } else {
+                e.i += 1;
+                double lb = e.winv * (double)(e.i - 1);
+                if (o_key(lb, e.p) >= q[root]) continue;
+                e.h = o_value3(P, e.K, e.i, e.winv);
+                st->points++;
+                uint64_t key = o_key(e.h, e.p);
+                if (key < q[root]) {
+                    uint32_t k = o_lemire(e.K, e.i, m);
+                    st->labels++;
+                    if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
+                }
+                if (e.i == P->imax) continue;
+                if (o_key(e.winv * (double)e.i, e.p) >= q[root]) continue;
+            }
+            buf[t++] = e;
+        }
+        s = t;
+    }
+    free(buf);
+    return O_OK;
+}
+
+/* Brute force: every point of every element's stream (to the end of the
+ * permutation for PMH2/4, to the cap for PMH1/3), then key_k = min over all
+ * points labelled k.  No stop rule is involved. */
+static int o_sign_brute(const o_params *P, uint64_t seedhash, const uint64_t *ids, const double *w,
+                        uint32_t n, uint64_t *keys, o_stats *st) {
+    const uint32_t m = P->m;
+    o_perm F;
+    if (o_perm_init(&F, m) != O_OK) { o_perm_free(&F); return O_ERR_OOM; }
+    for (uint32_t k = 0; k < m; ++k) keys[k] = O_EMPTY;
+    const uint64_t last = (P->variant == 2 || P->variant == 4) ? m : P->imax;
+    for (uint32_t p = 0; p < n; ++p) {
+        if (!(w[p] > 0.0)) continue;
+        double winv = 1.0 / w[p];
+        uint64_t K = o_elem_key(seedhash, ids[p]);
+        uint64_t T = 0;
+        o_perm_reset(&F);
+        for (uint64_t i = 1; i <= last; ++i) {
+            double x;
+            uint32_t k;
+            if (P->variant <= 2) {
+                T += o_spacing(P, K, i);
+                x = o_fixed_value(winv, T);
+            } else if (P->variant == 3) {
+                x = o_value3(P, K, i, winv);
+            } else {
+                x = o_value4(P, K, i, winv);
+            }
+            if (P->variant == 1 || P->variant == 3) k = o_lemire(K, i, m);
+            else k = o_perm_next(&F, K);
+            st->points++;
+            uint64_t key = o_key(x, p);
+            if (key < keys[k]) keys[k] = key;
+        }
+    }
+    o_perm_free(&F);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported API (ctypes).  Weights: 0 skips the element; negative, NaN,
+ * infinite or subnormal weights are rejected. */
+static int o_check_weights(const double *w, uint64_t n) {
+    for (uint64_t p = 0; p < n; ++p) {
+        double x = w[p];
+        if (x == 0.0) continue;
+        if (!(x > 0.0) || !(x <= 0x1.fffffffffffffp+1023) || x < 0x1p-1022) return O_ERR_WEIGHT;
+    }
+    return O_OK;
+}
+
+uint64_t or_seedhash(uint64_t seed) { return o_mix64(seed); }
+uint64_t or_mix64(uint64_t z) { return o_mix64(z); }
+uint64_t or_word(uint64_t K, uint64_t i, unsigned t) { return o_word(K, i, t); }
+double or_exp1_word(uint64_t w) { return o_exp1(w); }
+uint32_t or_lemire(uint64_t K, uint64_t i, uint32_t s) { return o_lemire(K, i, s); }
+double or_te(uint64_t K, uint64_t i, double lam, double c1, double c2, double c3) {
+    return o_te(K, i, lam, c1, c2, c3);
+}
+uint64_t or_key(double x, uint32_t p) { return o_key(x, p); }
+
+/* Constants of (variant, m) for inspection by the tests.  out[] receives
+ * PMH3: {lambda, c1, c2, c3}; PMH4 with index i: {lambda_i, c1_i, c2_i, c3_i,
+ * gamma_i, dgamma_i, delta}; PMH2 with index i: {beta_i}. */
+int or_constants(int variant, uint32_t m, uint32_t i, double *out) {
+    o_params P;
+    int rc = o_params_init(&P, variant, m);
+    if (rc) return rc;
+    if (variant == 2 && i >= 1 && i <= m) out[0] = P.beta[i];
+    if (variant == 3) { out[0] = P.lam3; out[1] = P.c1; out[2] = P.c2; out[3] = P.c3; }
+    if (variant == 4 && i < m) {
+        out[0] = P.lam4[i]; out[1] = P.c14[i]; out[2] = P.c24[i]; out[3] = P.c34[i];
+        out[4] = P.gam[i]; out[5] = P.dgam[i]; out[6] = P.delta;
+    }
+    o_params_free(&P);
+    return O_OK;
+}
+
+/* Point i of element K with weight inverse winv, for stream tests: value and
+ * label of points 1..count written to xs/ls (labels by Lemire for PMH1/3, by
+ * the Fisher-Yates steps 1..count for PMH2/4). */
+int or_stream(int variant, uint32_t m, uint64_t K, double winv, uint64_t count, double *xs,
+              uint32_t *ls) {
+    o_params P;
+    int rc = o_params_init(&P, variant, m);
+    if (rc) return rc;
+    o_perm F;
+    if (o_perm_init(&F, m) != O_OK) { o_perm_free(&F); o_params_free(&P); return O_ERR_OOM; }
+    o_perm_reset(&F);
+    uint64_t T = 0;
+    uint64_t last = (variant == 2 || variant == 4) ? m : P.imax;
+    for (uint64_t i = 1; i <= count && i <= last; ++i) {
+        if (variant <= 2) {
+            T += o_spacing(&P, K, i);
+            xs[i - 1] = o_fixed_value(winv, T);
+        } else if (variant == 3) {
+            xs[i - 1] = o_value3(&P, K, i, winv);
+        } else {
+            xs[i - 1] = o_value4(&P, K, i, winv);
+        }
+        ls[i - 1] = (variant == 1 || variant == 3) ? o_lemire(K, i, m) : o_perm_next(&F, K);
+    }
+    o_perm_free(&F);
+    o_params_free(&P);
+    return O_OK;
+}
+
+/* mode 0: sequential (Sec. 2.3-2.6), 1: interleaved (Sec. 2.7, PMH1/PMH3
+ * only), 2: brute force.  keys[m] out; stats[2] = {points, labels}. */
+int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+            uint64_t n, uint64_t *keys, uint64_t *stats) {
+    if ((!ids || !w) && n) return O_ERR_ARG;
+    if (n > O_MAX_SET) return O_ERR_SET_TOO_LARGE;
+    int rc = o_check_weights(w, n);
+    if (rc) return rc;
+    o_params P;
+    rc = o_params_init(&P, variant, m);
+    if (rc) return rc;
+    if (mode == 1 && variant != 1 && variant != 3) { o_params_free(&P); return O_ERR_ARG; }
+    uint64_t sh = o_mix64(seed);
+    o_stats st = {0, 0};
+    if (mode == 2) {
+        rc = o_sign_brute(&P, sh, ids, w, (uint32_t)n, keys, &st);
+    } else {
+        uint64_t *q = malloc(sizeof(uint64_t) * 2 * m);
+        o_perm F;
+        rc = o_perm_init(&F, m);
+        if (!q || rc) rc = O_ERR_OOM;
+        else if (mode == 0) o_sign_seq(&P, sh, ids, w, (uint32_t)n, q, &F, &st);
+        else rc = o_sign_interleaved(&P, sh, ids, w, (uint32_t)n, q, &st);
+        if (!rc) memcpy(keys, q + 1, sizeof(uint64_t) * m);
+        free(q);
+        o_perm_free(&F);
+    }
+    if (stats) { stats[0] = st.points; stats[1] = st.labels; }
+    o_params_free(&P);
+    return rc;
+}
+
+/* Decode keys into (idx, val, id): idx = position, val = truncated value,
+ * id = ids[idx]; an empty component gives idx 0xFFFFFFFF, val +inf, id 0. */
+void or_decode(const uint64_t *keys, uint64_t m, const uint64_t *ids, uint32_t *idx, double *val,
+               uint64_t *id) {
+    for (uint64_t k = 0; k < m; ++k) {
+        uint64_t key = keys[k];
+        if (key == O_EMPTY) {
+            if (idx) idx[k] = 0xFFFFFFFFu;
+            if (val) val[k] = INFINITY;
+            if (id) id[k] = 0;
+            continue;
+        }
+        uint32_t p = (uint32_t)(key & O_POS_MASK);
+        uint64_t vb = key & ~O_POS_MASK;
+        if (idx) idx[k] = p;
+        if (val) memcpy(&val[k], &vb, 8);
+        if (id) id[k] = ids[p];
+    }
+}
+
+/* Batch of sets in CSR form on a pool of threads, sequential algorithm per
+ * set.  keys_out: num_sets * m.  stats: {points, labels} summed. */
+typedef struct {
+    const o_params *P;
+    uint64_t sh;
+    const uint64_t *ids;
+    const double *w;
+    const uint64_t *off;
+    uint64_t num_sets;
+    uint64_t *keys;
+    volatile uint64_t next;
+    pthread_mutex_t lock;
+    uint64_t points, labels;
+    int rc;
+} o_batch;
+
+static void *o_batch_worker(void *arg) {
+    o_batch *B = arg;
+    const uint32_t m = B->P->m;
+    uint64_t *q = malloc(sizeof(uint64_t) * 2 * m);
+    o_perm F;
+    int rc = o_perm_init(&F, m);
+    o_stats st = {0, 0};
+    if (q && !rc) {
+        for (;;) {
+            uint64_t s = __atomic_fetch_add(&B->next, 1, __ATOMIC_RELAXED);
+            if (s >= B->num_sets) break;
+            uint64_t a = B->off[s], b = B->off[s + 1];
+            o_sign_seq(B->P, B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), q, &F, &st);
+            memcpy(B->keys + s * m, q + 1, sizeof(uint64_t) * m);
+        }
+    } else {
+        rc = O_ERR_OOM;
+    }
+    pthread_mutex_lock(&B->lock);
+    B->points += st.points;
+    B->labels += st.labels;
+    if (rc) B->rc = rc;
+    pthread_mutex_unlock(&B->lock);
+    free(q);
+    o_perm_free(&F);
+    return NULL;
+}
+
+int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+                  const uint64_t *offsets, uint64_t num_sets, uint64_t *keys_out, int nthreads,
+                  uint64_t *stats) {
+    if (!offsets || !keys_out) return O_ERR_ARG;
+    if (offsets[0] != 0) return O_ERR_ARG;
+    for (uint64_t s = 0; s < num_sets; ++s) {
+        if (offsets[s + 1] < offsets[s]) return O_ERR_ARG;
+        if (offsets[s + 1] - offsets[s] > O_MAX_SET) return O_ERR_SET_TOO_LARGE;
+    }
+    int rc = o_check_weights(w, offsets[num_sets]);
+    if (rc) return rc;
+    o_params P;
+    rc = o_params_init(&P, variant, m);
+    if (rc) return rc;
+    o_batch B = {&P, o_mix64(seed), ids, w, offsets, num_sets, keys_out, 0,
+                 PTHREAD_MUTEX_INITIALIZER, 0, 0, 0};
+    if (nthreads < 1) nthreads = 1;
+    pthread_t *th = malloc(sizeof(pthread_t) * nthreads);
+    int started = 0;
+    for (int t = 0; t < nthreads; ++t)
+        if (pthread_create(&th[t], NULL, o_batch_worker, &B) == 0) ++started;
+    if (started == 0) o_batch_worker(&B);
+    for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    free(th);
+    if (stats) { stats[0] = B.points; stats[1] = B.labels; }
+    o_params_free(&P);
+    return B.rc;
+}

@@ -1,0 +1,254 @@
+"""Seeded synthetic weighted-set generators (data only, no signature arithmetic).
+
+The paper evaluates on synthetic sets of random 64-bit ids with weights drawn
+from stated laws (Sec. 3, Sec. 3.1, Sec. 3.2); these generators produce the
+five workloads this library is measured and checked on.  Everything is a pure
+function of the data seed, returned as numpy arrays in CSR form:
+
+    ids      uint64[N]   element ids
+    weights  float64[N]  positive weights (normalised per set to sum 1)
+    offsets  uint64[S+1] set s owns elements offsets[s] .. offsets[s+1]-1
+
+Both the GPU tests/benchmark and the oracle-side tests draw their inputs from
+here; the module holds no part of the hashing method.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+U64 = np.uint64
+
+
+@dataclass
+class Batch:
+    ids: np.ndarray
+    weights: np.ndarray
+    offsets: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def num_sets(self) -> int:
+        return int(self.offsets.size - 1)
+
+    @property
+    def num_elements(self) -> int:
+        return int(self.offsets[-1])
+
+    def set(self, s: int):
+        a, b = int(self.offsets[s]), int(self.offsets[s + 1])
+        return self.ids[a:b], self.weights[a:b]
+
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.offsets).astype(np.int64)
+
+    def subset(self, sets) -> "Batch":
+        """Batch made of the given sets, in the given order."""
+        sets = np.asarray(sets, dtype=np.int64)
+        sizes = self.sizes()[sets]
+        off = np.zeros(sets.size + 1, dtype=np.uint64)
+        np.cumsum(sizes, out=off[1:])
+        idx = np.concatenate([np.arange(self.offsets[s], self.offsets[s + 1], dtype=np.int64)
+                              for s in sets]) if sets.size else np.zeros(0, dtype=np.int64)
+        return Batch(self.ids[idx], self.weights[idx], off, dict(self.meta, parent_sets=sets))
+
+
+def _rand_u64(rng: np.random.Generator, n: int) -> np.ndarray:
+    return rng.integers(0, np.iinfo(np.uint64).max, size=n, dtype=np.uint64, endpoint=True)
+
+
+def _normalise(w: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+    sizes = np.diff(offsets).astype(np.int64)
+    nz = sizes > 0
+    sums = np.zeros(sizes.size)
+    sums[nz] = np.add.reduceat(w, offsets[:-1][nz].astype(np.int64))
+    return w / np.repeat(np.where(sums > 0, sums, 1.0), sizes)
+
+
+def _offsets(sizes: np.ndarray) -> np.ndarray:
+    off = np.zeros(sizes.size + 1, dtype=np.uint64)
+    np.cumsum(sizes.astype(np.uint64), out=off[1:])
+    return off
+
+
+def _log_uniform_int(rng, lo: int, hi: int, n: int) -> np.ndarray:
+    """floor(exp(U * ln(hi + 1))) restricted to [lo, hi] (log-uniform law)."""
+    a, b = np.log(lo), np.log(hi + 1.0)
+    v = np.floor(np.exp(rng.uniform(a, b, size=n))).astype(np.int64)
+    return np.clip(v, lo, hi)
+
+
+def _distinct_fill(rng, ids: np.ndarray, offsets: np.ndarray) -> np.ndarray:
+    """Replace in-set duplicate ids by fresh random ids until every set is
+    duplicate-free (duplicates of random 64-bit ids are vanishingly rare, but
+    pool draws can repeat)."""
+    sizes = np.diff(offsets).astype(np.int64)
+    set_of = np.repeat(np.arange(sizes.size), sizes)
+    for _ in range(64):
+        order = np.lexsort((ids, set_of))
+        s_sorted, i_sorted = set_of[order], ids[order]
+        dup = np.zeros(ids.size, dtype=bool)
+        dup[1:] = (s_sorted[1:] == s_sorted[:-1]) & (i_sorted[1:] == i_sorted[:-1])
+        if not dup.any():
+            return ids
+        ids[order[dup]] = _rand_u64(rng, int(dup.sum()))
+    raise RuntimeError("could not make sets duplicate-free")
+
+
+# --------------------------------------------------------------------------- #
+# The five workloads.
+
+def plain_pairs(seed: int = 1, num_sets: int = 1000, n: int = 100, num_pairs: int = 200) -> Batch:
+    """1,000 sets of exactly 100 elements; uniform 64-bit ids; Exp(1) weights
+    normalised per set.  For j < 200, set 2j+1 shares 50 random ids of set 2j
+    (with fresh weights), so the 200 pairs (2j, 2j+1) have nonzero J_P."""
+    rng = np.random.default_rng(seed)
+    ids = _rand_u64(rng, num_sets * n)
+    half = n // 2
+    for j in range(num_pairs):
+        a, b = 2 * j * n, (2 * j + 1) * n
+        pick = rng.choice(n, size=half, replace=False)
+        ids[b:b + half] = ids[a + pick]
+    w = rng.exponential(1.0, size=num_sets * n)
+    w = np.where(w > 0, w, 1.0)
+    off = _offsets(np.full(num_sets, n))
+    ids = _distinct_fill(rng, ids, off)
+    return Batch(ids, _normalise(w, off), off,
+                 dict(name="plain_pairs", seed=seed, pairs=[(2 * j, 2 * j + 1) for j in range(num_pairs)]))
+
+
+def mixed_sizes(seed: int = 2, num_sets: int = 100_000, n_lo: int = 1, n_hi: int = 10_000,
+                pool_size: int = 1_000_000, pool_frac: float = 0.2, pareto_shape: float = 1.5) -> Batch:
+    """Sets with log-uniform sizes in [1, 10^4]; each id comes from a shared
+    pool of 10^6 ids with probability 0.2 (so sets overlap), else a fresh
+    uniform 64-bit id; Pareto(x_m = 1, shape 1.5) weights normalised per set."""
+    rng = np.random.default_rng(seed)
+    sizes = _log_uniform_int(rng, n_lo, n_hi, num_sets)
+    off = _offsets(sizes)
+    N = int(off[-1])
+    pool = _rand_u64(rng, pool_size)
+    ids = _rand_u64(rng, N)
+    from_pool = rng.random(N) < pool_frac
+    ids[from_pool] = pool[rng.integers(0, pool_size, size=int(from_pool.sum()))]
+    ids = _distinct_fill(rng, ids, off)
+    w = (1.0 - rng.random(N)) ** (-1.0 / pareto_shape)
+    return Batch(ids, _normalise(w, off), off, dict(name="mixed_sizes", seed=seed))
+
+
+def skewed(seed: int = 3, num_sets: int = 10_000, large_frac: float = 0.1,
+           small=(10, 100), large=(100_000, 1_000_000)) -> Batch:
+    """Heavy size skew: 90% of sets log-uniform in [10, 100] elements, 10% in
+    [10^5, 10^6], at random positions; uniform ids; weights uniform on (0, 1]
+    normalised per set."""
+    rng = np.random.default_rng(seed)
+    is_large = rng.random(num_sets) < large_frac
+    sizes = np.where(is_large, _log_uniform_int(rng, large[0], large[1], num_sets),
+                     _log_uniform_int(rng, small[0], small[1], num_sets))
+    off = _offsets(sizes)
+    N = int(off[-1])
+    ids = _distinct_fill(rng, _rand_u64(rng, N), off)
+    w = 1.0 - rng.random(N)  # (0, 1]
+    return Batch(ids, _normalise(w, off), off, dict(name="skewed", seed=seed))
+
+
+def serving_requests(seed: int = 4, num_requests: int = 220_000, rate: float = 50_000.0,
+                     n_lo: int = 10, n_hi: int = 100_000) -> Batch:
+    """Single-set requests with Poisson arrivals (exponential inter-arrival
+    times at the given rate, seconds in meta['arrival']), log-uniform sizes in
+    [10, 10^5], uniform ids, Exp(1) weights normalised per set."""
+    rng = np.random.default_rng(seed)
+    sizes = _log_uniform_int(rng, n_lo, n_hi, num_requests)
+    off = _offsets(sizes)
+    N = int(off[-1])
+    ids = _distinct_fill(rng, _rand_u64(rng, N), off)
+    w = rng.exponential(1.0, size=N)
+    w = np.where(w > 0, w, 1.0)
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=num_requests))
+    return Batch(ids, _normalise(w, off), off,
+                 dict(name="serving_requests", seed=seed, rate=rate, arrival=arrival))
+
+
+def _zipf_ranks(rng, a: float, n_max: int, size: int) -> np.ndarray:
+    """Zipf(a) ranks truncated to [1, n_max] (draws above n_max are redrawn)."""
+    out = rng.zipf(a, size=size)
+    bad = out > n_max
+    while bad.any():
+        out[bad] = rng.zipf(a, size=int(bad.sum()))
+        bad = out > n_max
+    return out.astype(np.uint64)
+
+
+def large_uniform(seed: int = 5, num_sets: int = 1_000_000, n: int = 1000, universe: int = 100_000_000,
+                  zipf_a: float = 1.1) -> Batch:
+    """Sets of exactly 1,000 distinct ids whose popularity follows Zipf(1.1)
+    over a universe of 10^8 ids (id = rank), drawn without replacement within
+    a set; log-normal(0, 1) weights normalised per set."""
+    rng = np.random.default_rng(seed)
+    ids = np.empty(num_sets * n, dtype=np.uint64)
+    block = 2000
+    for s0 in range(0, num_sets, block):
+        s1 = min(num_sets, s0 + block)
+        for s in range(s0, s1):
+            got = np.empty(0, dtype=np.uint64)
+            draw = 4 * n
+            while got.size < n:
+                cand = _zipf_ranks(rng, zipf_a, universe, draw)
+                got = np.concatenate([got, cand])
+                _, first = np.unique(got, return_index=True)
+                got = got[np.sort(first)]
+                draw *= 2
+            ids[s * n:(s + 1) * n] = got[:n]
+    off = _offsets(np.full(num_sets, n))
+    w = np.exp(rng.standard_normal(num_sets * n))
+    return Batch(ids, _normalise(w, off), off, dict(name="large_uniform", seed=seed))
+
+
+def weight_pairs(W, num_pairs: int, seed: int = 11):
+    """Pairs of weighted sets realising a multiset W of weight pairs (Sec. 3.1):
+    every pair (wA, wB) in W becomes one fresh random element that gets weight
+    wA in set A and wB in set B (absent where the weight is 0).  Returns a
+    Batch with sets (2j, 2j+1) forming pair j."""
+    rng = np.random.default_rng(seed)
+    W = [(float(a), float(b)) for a, b in W]
+    ids_list, w_list, sizes = [], [], []
+    for _ in range(num_pairs):
+        e = _rand_u64(rng, len(W))
+        for side in (0, 1):
+            sel = [k for k, pr in enumerate(W) if pr[side] > 0]
+            ids_list.append(e[sel])
+            w_list.append(np.array([W[k][side] for k in sel], dtype=np.float64))
+            sizes.append(len(sel))
+    off = _offsets(np.array(sizes))
+    return Batch(np.concatenate(ids_list), np.concatenate(w_list), off,
+                 dict(name="weight_pairs", W=W, seed=seed))
+
+
+def random_sets(seed: int, num_sets: int, n_lo: int, n_hi: int, weight_law: str = "exp") -> Batch:
+    """Small generic batches for tests: sizes uniform in [n_lo, n_hi]."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(n_lo, n_hi + 1, size=num_sets)
+    off = _offsets(sizes)
+    N = int(off[-1])
+    ids = _distinct_fill(rng, _rand_u64(rng, N), off)
+    if weight_law == "exp":
+        w = rng.exponential(1.0, size=N)
+        w = np.where(w > 0, w, 1.0)
+    elif weight_law == "pareto":
+        w = (1.0 - rng.random(N)) ** (-1.0 / 1.5)
+    elif weight_law == "ones":
+        w = np.ones(N)
+    elif weight_law == "wide":  # log-uniform over many decades
+        w = np.exp(rng.uniform(np.log(1e-300), np.log(1e300), size=N))
+    else:
+        raise ValueError(weight_law)
+    return Batch(ids, w, off, dict(name="random_sets", seed=seed, law=weight_law))
+
+
+WORKLOADS = {
+    "plain_pairs": plain_pairs,
+    "mixed_sizes": mixed_sizes,
+    "skewed": skewed,
+    "serving_requests": serving_requests,
+    "large_uniform": large_uniform,
+}
