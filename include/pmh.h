@@ -1,0 +1,199 @@
+/*
+ * pmh.h -- C ABI of the MI355X ProbMinHash signature library (libpmh.so).
+ *
+ * Computes ProbMinHash signatures of weighted sets as defined in
+ *   O. Ertl, "ProbMinHash -- A Class of Locality-Sensitive Hash Algorithms for
+ *   the (Probability) Jaccard Similarity", IEEE TKDE 2020 (arXiv 1911.00675).
+ *
+ * Problem statement (Sec. 1, eq. (1) and eq. (6)): a weighted set is a map
+ * w: D -> [0, inf) over 64-bit element ids; its signature z_1..z_m holds, for
+ * every component k, the element whose hash h_k(d) ~ Exp(lambda w(d)) is
+ * smallest.  The hashes come from per-element point streams (Sec. 2.1) of the
+ * four variants ProbMinHash1-4 (Sec. 2.3-2.6).  Two signatures estimate the
+ * probability Jaccard similarity J_P by the fraction of equal components
+ * (eq. (3)).
+ *
+ * Conventions for every entry point:
+ *   * Pointers marked [device] are device memory of the current HIP device,
+ *     owned by the caller (e.g. a torch tensor's data_ptr); the library never
+ *     frees them.  Pointers marked [host] are host memory.
+ *   * `stream` is a hipStream_t (NULL = the legacy default stream).  Device
+ *     work is enqueued asynchronously on it and ordered with the caller's
+ *     other work on that stream.
+ *   * Return value: PMH_OK or a pmh_status code; argument errors are reported
+ *     synchronously, before anything is enqueued.  Errors found by kernels
+ *     (invalid weights, oversize sets) are sticky in the context and returned
+ *     by pmh_get_status().
+ *   * A context may be used by one stream at a time (its work list and counter
+ *     are shared by its calls); use one context per concurrent stream.
+ *
+ * Input layout (CSR): set s owns elements offsets[s] .. offsets[s+1]-1 of the
+ * arrays ids (uint64) and weights (float64); offsets has num_sets+1 entries
+ * with offsets[0] = 0.  A weight of 0 removes the element (Sec. 1.1); a
+ * negative, NaN, infinite or subnormal weight is skipped and reported as
+ * PMH_ERR_WEIGHT.  At most 2^20 elements per set (PMH_ERR_SET_TOO_LARGE; such
+ * a set's signature is left empty).  Duplicate ids within a set are not
+ * checked.
+ *
+ * Output layout (SoA, row-major [num_sets][m]); each output pointer may be
+ * NULL to skip it:
+ *   out_idx[s*m+k]  uint32  position of z_k within set s (0xFFFFFFFF: empty)
+ *   out_val[s*m+k]  float64 the winning point value, truncated to 32 fraction
+ *                           bits (+inf: empty)
+ *   out_id[s*m+k]   uint64  ids[offsets[s] + out_idx] (0: empty)
+ *   out_keys[s*m+k] uint64  packed key (value bits | position), all ones: empty
+ *
+ * Determinism: the signature is a pure function of (seed, m, variant, set);
+ * it does not depend on element order, batch composition, launch shape or
+ * tuning, and matches the CPU reference bit for bit.
+ */
+#ifndef PMH_H
+#define PMH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pmh_ctx pmh_ctx;
+typedef struct pmh_server pmh_server;
+
+enum {
+  PMH_OK = 0,
+  PMH_ERR_ARG = 1,            /* null pointer, bad count or bad enum */
+  PMH_ERR_M_RANGE = 2,        /* m outside [1, pmh_max_m()] */
+  PMH_ERR_VARIANT_M = 3,      /* m = 1 with ProbMinHash3/4 (Sec. 2.5, 2.6 need m >= 2) */
+  PMH_ERR_WEIGHT = 4,         /* invalid weight seen by a kernel */
+  PMH_ERR_SET_TOO_LARGE = 5,  /* set above 2^20 elements seen by a kernel */
+  PMH_ERR_DEVICE = 6,         /* HIP runtime error */
+  PMH_ERR_OOM = 7,            /* device or host allocation failed */
+  PMH_ERR_BUSY = 8,           /* serving queue full */
+  PMH_ERR_NOT_READY = 9       /* serving request still in flight */
+};
+
+/* Tunables of the per-set schedule.  None of them changes any result. */
+typedef struct {
+  double c0;          /* first value threshold T0 = m (ln m + c0) / sum(w) */
+  double grow;        /* threshold growth per extra round (> 1) */
+  int max_rounds;     /* rounds before the unbounded final round (>= 1) */
+  double chain_expect;/* elements expecting more points go to wave-chain mode */
+  int lane_budget;    /* lane-mode points before an element moves to chain mode */
+  int waves;          /* wavefronts per workgroup: 1, 2 or 4 */
+  int kmax_refresh;   /* element batches between stop-limit refreshes (>= 1) */
+  int blocks_per_cu;  /* persistent grid = CUs * this (0: occupancy limit) */
+} pmh_tuning;
+
+/* Create a context for (seed, m, variant) on the current device.  variant is
+ * 1..4 for ProbMinHash1..4.  Builds the per-m constant tables on the device
+ * (beta_i of Sec. 2.4; lambda, sampler constants c1..c3 of Sec. 2.8; lambda_i,
+ * gamma_i, delta of Sec. 2.6).  Synchronous.  *out receives the context. */
+int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out);
+
+/* Free the context and its device memory (synchronizes the device). */
+void pmh_destroy(pmh_ctx* ctx);
+
+/* Largest supported m on the current device (LDS-limited, <= 16384). */
+uint32_t pmh_max_m(int variant);
+
+/* Human-readable text for a status code (static storage). */
+const char* pmh_status_str(int status);
+
+/* Signatures of num_sets weighted sets in one persistent launch (plus one
+ * ordering kernel): sets are taken heavy-first from a device work list.
+ * ids, weights, offsets [device]; outputs [device] or NULL. */
+int pmh_hash_sets(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                  uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
+                  uint64_t* out_keys, void* stream);
+
+/* Same result with one kernel launch per set (the plain form). */
+int pmh_hash_sets_plain(pmh_ctx* ctx, const uint64_t* ids, const double* weights,
+                        const uint64_t* offsets, uint64_t num_sets, uint32_t* out_idx,
+                        double* out_val, uint64_t* out_id, uint64_t* out_keys, void* stream);
+
+/* Same result as pmh_hash_sets, replayed from a HIP graph captured on the
+ * first call with this exact argument tuple (re-captured when it changes). */
+int pmh_hash_sets_graph(pmh_ctx* ctx, const uint64_t* ids, const double* weights,
+                        const uint64_t* offsets, uint64_t num_sets, uint32_t* out_idx,
+                        double* out_val, uint64_t* out_id, uint64_t* out_keys, void* stream);
+
+/* Synchronize `stream`, then return and clear the context's sticky kernel
+ * errors (PMH_ERR_WEIGHT, PMH_ERR_SET_TOO_LARGE) or PMH_OK. */
+int pmh_get_status(pmh_ctx* ctx, void* stream);
+
+int pmh_set_tuning(pmh_ctx* ctx, const pmh_tuning* t);
+int pmh_get_tuning(const pmh_ctx* ctx, pmh_tuning* t);
+
+/* Time candidate schedules on the given batch ([device] inputs, the batch is
+ * hashed trials times per candidate) and keep the fastest in the context;
+ * *best (host, may be NULL) receives it.  Synchronous. */
+int pmh_autotune(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                 uint64_t num_sets, int trials, void* stream, pmh_tuning* best);
+
+/* Estimator of eq. (3) for one pair of signatures of size m, [host] inputs:
+ * fraction of components k with idA[k] == idB[k], empty components (idx
+ * 0xFFFFFFFF) never counting as equal.  *out [host]. */
+int pmh_estimate(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB, const uint32_t* idxB,
+                 uint32_t m, double* out);
+
+/* Equal-component counts for `pairs` signature pairs, [device] inputs laid out
+ * [pairs][m]; counts[pairs] uint32 [device].  Divide by m for eq. (3). */
+int pmh_estimate_pairs(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB,
+                       const uint32_t* idxB, uint32_t m, uint64_t pairs, uint32_t* counts,
+                       void* stream);
+
+/* All-pairs equal-component counts over k signatures of m 32-bit
+ * fingerprints fp[k][m] [device] (0 = empty component, never equal);
+ * counts[k][k] uint16 [device], saturating at 65535. */
+int pmh_allpairs_counts(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts, void* stream);
+
+/* Copy a constant table to [host] out (count doubles).  which: 0 beta (PMH2,
+ * m+1), 1 lambda_i, 2 c1_i, 3 c2_i, 4 c3_i, 5 gamma_i, 6 dgamma_i (PMH4, m
+ * each), 7 scalars {lambda, c1, c2, c3, delta, 0, 0, 0} (8), 8 expm1
+ * coefficients (19).  Synchronous. */
+int pmh_get_table(pmh_ctx* ctx, int which, double* out, uint32_t count);
+
+/* Evaluate one primitive of the random streams elementwise on [device]
+ * arrays (for validation): what 0 log(in), 1 log1p(in), 2 expm1(in),
+ * 3 Exp(1) from word in_u, 4 mix64(in_u), 5 truncated exponential of element
+ * key in_u[k] at point k+1 (PMH3 constants), 6 Lemire(m) label of that point,
+ * 7 ProbMinHash1 fixed-point spacing of that point. */
+int pmh_debug_eval(pmh_ctx* ctx, int what, const double* in, const uint64_t* in_u, double* out,
+                   uint64_t* out_u, uint64_t n, void* stream);
+
+/* ---- serving: continuous batching of single-set requests ----------------
+ * A dispatcher thread owned by the server admits queued requests into free
+ * slots (a slot = stream + device buffers) as long as the slot's element
+ * budget and the server's total HBM budget allow, copies them host->device,
+ * runs the batched kernels and copies the signatures back.  Requests that
+ * arrive while other batches are on the GPU are admitted as soon as a slot
+ * frees; several slots run concurrently on separate streams.  Results are
+ * identical to pmh_hash_sets on the same set. */
+int pmh_server_create(pmh_ctx* ctx, int slots, uint64_t slot_elems, uint32_t slot_sets,
+                      uint64_t hbm_budget_bytes, pmh_server** out);
+/* Copy a request in ([host] ids, weights of n elements); *ticket receives its
+ * handle.  PMH_ERR_BUSY when the pending queue is full. */
+int pmh_server_submit(pmh_server* s, const uint64_t* ids, const double* weights, uint32_t n,
+                      uint64_t* ticket);
+/* PMH_OK and the signature ([host] outputs of m entries, any may be NULL) when
+ * the request is done, PMH_ERR_NOT_READY otherwise.  Results stay available
+ * until fetched once. */
+int pmh_server_fetch(pmh_server* s, uint64_t ticket, uint32_t* idx, double* val, uint64_t* id);
+/* Open-loop replay: submits request r at arrival[r] seconds after the start
+ * (busy-waiting for the scheduled time), then waits for all results.
+ * latency[r] (host, seconds) = completion time - scheduled arrival.  Requests
+ * are given in CSR form on the host; signatures are written to [host]
+ * out_idx/out_id ([num][m], may be NULL).  *wall receives the elapsed time. */
+int pmh_server_replay(pmh_server* s, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                      uint64_t num, const double* arrival, double* latency, uint32_t* out_idx,
+                      uint64_t* out_id, double* wall);
+/* Counters: [0] batches launched, [1] requests done, [2] max requests in one
+ * batch, [3] max concurrent slots busy, [4] requests that waited for a slot. */
+int pmh_server_stats(pmh_server* s, uint64_t* out5);
+void pmh_server_destroy(pmh_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMH_H */

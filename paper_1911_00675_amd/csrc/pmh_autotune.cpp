@@ -1,0 +1,117 @@
+// Schedule autotuner: coordinate descent over the per-set schedule knobs,
+// timing the batched launch with HIP events on the caller's batch.  None of
+// the knobs changes a result; they trade points generated against launch
+// shape and occupancy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/pmh.h"
+#include "pmh_runtime.h"
+
+using namespace pmh;
+
+namespace {
+
+double time_once(pmh_ctx* c, const HashArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int* rc) {
+  (void)hipEventRecord(e0, s);
+  *rc = enqueue_batched(c, a, &c->work, s);
+  (void)hipEventRecord(e1, s);
+  if (*rc) return 1e30;
+  if (hipEventSynchronize(e1) != hipSuccess) {
+    *rc = PMH_ERR_DEVICE;
+    return 1e30;
+  }
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  return ms;
+}
+
+double measure(pmh_ctx* c, const HashArgs& base, int trials, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int* rc) {
+  HashArgs a = make_args(c, base.ids, base.w, base.off, base.num_sets, nullptr, nullptr, nullptr, nullptr, &c->work);
+  time_once(c, a, s, e0, e1, rc);  // warm-up
+  if (*rc) return 1e30;
+  std::vector<double> v;
+  for (int t = 0; t < trials; ++t) {
+    v.push_back(time_once(c, a, s, e0, e1, rc));
+    if (*rc) return 1e30;
+  }
+  std::sort(v.begin(), v.end());
+  return v[v.size() / 2];
+}
+
+}  // namespace
+
+extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
+                            int trials, void* stream, pmh_tuning* best_out) {
+  if (!c || !ids || !w || !off || num_sets == 0 || num_sets >= 0xFFFFFFFFull) return PMH_ERR_ARG;
+  if (trials < 1) trials = 1;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_work(c, &c->work, num_sets);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PMH_ERR_DEVICE;
+  HashArgs base = make_args(c, ids, w, off, num_sets, nullptr, nullptr, nullptr, nullptr, &c->work);
+  Tuning best = c->tune;
+  double best_ms = measure(c, base, trials, s, e0, e1, &rc);
+  // coordinate descent, one knob at a time, two sweeps
+  for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
+    for (int knob = 0; knob < 6 && !rc; ++knob) {
+      std::vector<Tuning> cands;
+      auto add = [&](auto setter) {
+        Tuning t = best;
+        setter(t);
+        cands.push_back(t);
+      };
+      switch (knob) {
+        case 0:
+          for (int wv : {1, 2, 4})
+            if (lds_bytes(c->variant, c->m, wv) <= c->lds_limit) add([&](Tuning& t) { t.waves = wv; });
+          break;
+        case 1:
+          for (double c0 : {1.0, 2.0, 3.0, 4.0, 6.0}) add([&](Tuning& t) { t.c0 = c0; });
+          break;
+        case 2:
+          for (double ce : {4.0, 8.0, 12.0, 24.0, 48.0}) add([&](Tuning& t) { t.chain_expect = ce; });
+          break;
+        case 3:
+          for (int lb : {2, 4, 8, 16}) add([&](Tuning& t) { t.lane_budget = lb; });
+          break;
+        case 4:
+          for (int kr : {1, 4, 16}) add([&](Tuning& t) { t.kmax_refresh = kr; });
+          break;
+        case 5:
+          for (int bp : {0, 1, 2, 4, 8}) add([&](Tuning& t) { t.blocks_per_cu = bp; });
+          break;
+      }
+      for (const Tuning& t : cands) {
+        c->tune = t;
+        base = make_args(c, ids, w, off, num_sets, nullptr, nullptr, nullptr, nullptr, &c->work);
+        const double ms = measure(c, base, trials, s, e0, e1, &rc);
+        if (rc) break;
+        if (ms < best_ms * 0.98) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+    }
+  }
+  c->tune = best;
+  c->tune_version++;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_out) {
+    best_out->c0 = best.c0;
+    best_out->grow = best.grow;
+    best_out->max_rounds = best.max_rounds;
+    best_out->chain_expect = best.chain_expect;
+    best_out->lane_budget = best.lane_budget;
+    best_out->waves = best.waves;
+    best_out->kmax_refresh = best.kmax_refresh;
+    best_out->blocks_per_cu = best.blocks_per_cu;
+  }
+  return rc;
+}

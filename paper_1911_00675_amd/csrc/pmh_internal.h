@@ -1,0 +1,87 @@
+// Internal interface between the HIP kernels (pmh_kernels.hip) and the host
+// runtime (pmh_runtime.cpp).  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmh {
+
+constexpr uint64_t kPhi = 0x9E3779B97F4A7C15ull;   // SplitMix64 increment
+constexpr uint64_t kEmptyKey = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint64_t kPosMask = 0xFFFFFull;          // 20 position bits
+constexpr uint64_t kMaxSet = 1ull << 20;
+constexpr uint32_t kMaxM = 16384;
+
+// device status bits (sticky until read)
+constexpr uint32_t kStatusWeight = 1u;      // a negative/NaN/inf/subnormal weight was skipped
+constexpr uint32_t kStatusSetTooLarge = 2u; // a set above 2^20 elements was left empty
+
+// Per-(variant, m) constant tables in device memory, computed on the device by
+// the table-init kernel from the spec formulas.
+struct Tables {
+  double* beta;   // PMH2: [m+1], beta[i] = m/(m-i+1)
+  double* lam;    // PMH4: [m], lambda_i = log(1 + 1/(m-i)), i = 1..m-1
+  double* c1;     // PMH4: [m] sampler constants per i
+  double* c2;
+  double* c3;
+  double* gam;    // PMH4: [m], gamma_0 = 0, gamma_i = log(1 + i/(m-i))/lambda_1
+  double* dgam;   // PMH4: [m], gamma_i - gamma_{i-1}
+  double* expm1c; // [19] Taylor coefficients 1/k! built by repeated division
+  double* scal;   // [8]: lambda, c1, c2, c3 (PMH3), delta (PMH4)
+};
+
+// Tunables of the per-set algorithm (chosen by the autotuner or defaults).
+struct Tuning {
+  double c0 = 3.0;          // first threshold T0 = m (ln m + c0) / sum(w)
+  double grow = 2.0;        // T_{r+1} = grow * T_r
+  int max_rounds = 4;       // the last round runs with T = +inf
+  double chain_expect = 12; // elements expecting more points than this go to chain mode
+  int lane_budget = 8;      // lane-mode steps before an element moves to chain mode
+  int waves = 4;            // waves per workgroup
+  int kmax_refresh = 8;     // element batches between stop-limit refreshes
+  int blocks_per_cu = 0;    // persistent grid = CUs * this (0: occupancy limit)
+};
+
+struct HashArgs {
+  const uint64_t* ids;
+  const double* w;
+  const uint64_t* off;       // [num_sets + 1]
+  uint64_t num_sets;
+  uint32_t* out_idx;         // [num_sets * m] or null
+  double* out_val;           // [num_sets * m] or null
+  uint64_t* out_id;          // [num_sets * m] or null
+  uint64_t* out_keys;        // [num_sets * m] or null
+  uint64_t seedhash;
+  uint32_t m;
+  uint32_t imax;
+  Tables t;
+  double c0, grow, chain_expect;
+  int max_rounds, lane_budget, kmax_refresh;
+  uint32_t* status;          // device status word
+  const uint32_t* order;     // work list (set indices), heavy first
+  uint32_t* counter;         // persistent work counter (zeroed by the order kernel)
+  uint32_t num_items;
+  uint64_t* points;          // optional: points generated (profiling), or null
+};
+
+// launchers (pmh_kernels.hip)
+hipError_t launch_init_tables(int variant, uint32_t m, Tables t, hipStream_t s);
+hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t* order, uint32_t* counter,
+                        uint32_t* status, hipStream_t s);
+hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size_t lds,
+                       hipStream_t s);
+hipError_t launch_hash_one(int variant, const HashArgs& a, uint64_t set, int waves, size_t lds,
+                           hipStream_t s);
+hipError_t occupancy(int variant, int waves, size_t lds, int* blocks_per_cu);
+size_t lds_bytes(int variant, uint32_t m, int waves);   // dynamic LDS of k_hash_*
+size_t lds_static_bytes();                                // its static LDS
+hipError_t launch_estimate(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB,
+                           const uint32_t* idxB, uint32_t m, uint64_t pairs, uint32_t* counts,
+                           hipStream_t s);
+hipError_t launch_allpairs(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts,
+                           hipStream_t s);
+hipError_t launch_debug_eval(int what, const double* in, const uint64_t* in_u, double* out,
+                             uint64_t* out_u, uint64_t n, uint32_t m, int variant, Tables t,
+                             hipStream_t s);
+
+}  // namespace pmh

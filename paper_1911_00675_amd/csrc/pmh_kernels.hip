@@ -1,0 +1,860 @@
+// HIP kernels for ProbMinHash signatures on gfx950 (MI355X).
+//
+// O. Ertl, "ProbMinHash -- A Class of Locality-Sensitive Hash Algorithms for the
+// (Probability) Jaccard Similarity", IEEE TKDE 2020.
+//
+// One workgroup computes the signature of one weighted set; a persistent grid
+// pulls sets from a heavy-first work list.  Per set:
+//
+//   * keys[m] (u64, LDS) hold the running minimum of Key(x, p) per label, where
+//     Key packs the point value's top bits and the element position, so a
+//     single 64-bit atomic min on LDS performs "if h < q_k then q_k = h,
+//     z_k = d" of the paper's algorithms (Sec. 2, basic structure).
+//   * Points are generated in rounds of increasing value threshold T (a
+//     schedule in the spirit of the interleaved processing of Sec. 2.7): round r
+//     generates every point below T_r of every element and applies those below
+//     the running stop limit max_k q_k (Sec. 2, "stop limit").  Once the stop
+//     limit falls below T_r all keys are final.  The result is the exact
+//     minimum over all points, independent of the processing order.
+//   * Elements with short expected streams run one per lane ("lane mode");
+//     long streams are handed to a queue and run 64 consecutive points per
+//     wavefront ("chain mode"): ProbMinHash1/2 spacings are 64-bit fixed point
+//     so a wave prefix sum reproduces the sequential accumulation exactly;
+//     ProbMinHash3/4 points are independent per index; ProbMinHash2/4 resolve
+//     64 Fisher-Yates steps (Sec. 2.4) per wave with in-register dependency
+//     chasing.
+//   * Random words are counter-based (SplitMix64 addressed by element key and
+//     point index) so any lane can generate any point.
+//
+// All floating-point arithmetic is IEEE binary64 without contraction; fma is
+// used only where the stream definitions say so.
+
+#include <float.h>
+
+#include "pmh_internal.h"
+
+namespace pmh {
+namespace {
+
+constexpr double kLn2Hi = 0x1.62e42fefa0000p-1;  // ln 2 rounded to 36 bits
+constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
+constexpr uint32_t kFyLaneSteps = 4;             // lane-mode Fisher-Yates steps kept in registers
+constexpr uint32_t kEpt = 2;                     // elements per thread per batch
+
+// ---------------------------------------------------------------- randomness
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Word slot t of point i of element K is mix64(K + ((i << 8) + t + 1) * phi);
+// pbase folds the point-independent part so slot t costs one add.
+__device__ __forceinline__ uint64_t pbase(uint64_t K, uint32_t i) {
+  return K + (uint64_t)((i << 8) + 1u) * kPhi;
+}
+__device__ __forceinline__ uint64_t word(uint64_t pb, uint32_t t) { return mix64(pb + (uint64_t)t * kPhi); }
+__device__ __forceinline__ double u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
+__device__ __forceinline__ double upos(uint64_t w) { return (double)((w >> 11) + 1) * 0x1p-53; }
+
+// ln x = e ln 2 + 2 atanh(s), x = 2^e f, f in [sqrt(1/2), sqrt(2)), s = (f-1)/(f+1).
+__device__ __forceinline__ double spec_log(double x) {
+  uint64_t b = (uint64_t)__double_as_longlong(x);
+  int e = (int)((b >> 52) & 0x7FF) - 1023;
+  uint64_t mant = b & 0xFFFFFFFFFFFFFull;
+  const bool halve = mant >= 0x6A09E667F3BCDull;
+  e += halve ? 1 : 0;
+  double f = __longlong_as_double((long long)(mant | (halve ? (1022ull << 52) : (1023ull << 52))));
+  double s = (f - 1.0) / (f + 1.0);
+  double t = s * s;
+  double q = 2.0 / 21.0;
+  q = __builtin_fma(q, t, 2.0 / 19.0);
+  q = __builtin_fma(q, t, 2.0 / 17.0);
+  q = __builtin_fma(q, t, 2.0 / 15.0);
+  q = __builtin_fma(q, t, 2.0 / 13.0);
+  q = __builtin_fma(q, t, 2.0 / 11.0);
+  q = __builtin_fma(q, t, 2.0 / 9.0);
+  q = __builtin_fma(q, t, 2.0 / 7.0);
+  q = __builtin_fma(q, t, 2.0 / 5.0);
+  q = __builtin_fma(q, t, 2.0 / 3.0);
+  double lf = 2.0 * s + (s * t) * q;
+  double de = (double)e;
+  return de * kLn2Hi + (de * kLn2Lo + lf);
+}
+
+// log(1 + u), u > 0; per-m constants only.
+__device__ double spec_log1p(double u) {
+  if (u > 1.0) return spec_log(1.0 + u);
+  double s = u / (2.0 + u);
+  double t = s * s;
+  double q = 2.0 / 49.0;
+  for (int j = 23; j >= 1; --j) q = __builtin_fma(q, t, 2.0 / (double)(2 * j + 1));
+  return 2.0 * s + (s * t) * q;
+}
+
+__device__ __forceinline__ double spec_expm1(double t, const double* c) {
+  double p = c[18];
+  for (int k = 17; k >= 1; --k) p = __builtin_fma(p, t, c[k]);
+  return p * t;
+}
+
+__device__ __forceinline__ double exp1(uint64_t w) { return 0.0 - spec_log(upos(w)); }
+
+// Rejection part of the truncated-exponential sampler (Sec. 2.8).
+__device__ __attribute__((noinline)) double te_slow(uint64_t pb, double lam, double c1, double c2,
+                                                    double c3, const double* em) {
+  double x = 0.0;
+  for (uint32_t it = 0; it < 32; ++it) {
+    x = u53(word(pb, 16u + 2u * it));
+    if (x < c2) return x;
+    double y = 0.5 * u53(word(pb, 17u + 2u * it));
+    if (y > 1.0 - x) {
+      x = 1.0 - x;
+      y = 1.0 - y;
+    }
+    if (x <= c3 * (1.0 - y)) return x;
+    double yc = y * c1;
+    if (yc <= 1.0 - x) return x;
+    if (yc * lam <= spec_expm1(lam * (1.0 - x), em)) return x;
+  }
+  return x;
+}
+// Exp(lam; 0, 1): the rectangle below e^-lam first (taken with probability
+// lam/(e^lam - 1)), rejection otherwise.
+__device__ __forceinline__ double trunc_exp(uint64_t pb, double lam, double c1, double c2, double c3,
+                                            const double* em) {
+  double x = c1 * u53(mix64(pb));
+  if (x < 1.0) return x;
+  return te_slow(pb, lam, c1, c2, c3, em);
+}
+
+__device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_t s, uint64_t prod) {
+  uint32_t thr = (0u - s) % s;
+  uint32_t lo = (uint32_t)prod;
+  for (uint32_t r = 1; lo < thr && r <= 8; ++r) {
+    uint64_t x = word(pb, 1u + r) >> 32;
+    prod = x * (uint64_t)s;
+    lo = (uint32_t)prod;
+  }
+  return prod;
+}
+// Uniform integer in [0, s) (Lemire's multiply-shift with rejection).
+__device__ __forceinline__ uint32_t lemire(uint64_t pb, uint32_t s) {
+  uint64_t x = word(pb, 1u) >> 32;
+  uint64_t prod = x * (uint64_t)s;
+  if ((uint32_t)prod < s) prod = lemire_redraw(pb, s, prod);
+  return (uint32_t)(prod >> 32);
+}
+
+__device__ __forceinline__ uint64_t make_key(double x, uint32_t p) {
+  return ((uint64_t)__double_as_longlong(x) & ~kPosMask) | (uint64_t)p;
+}
+__device__ __forceinline__ bool weight_ok(double w) { return w >= 0x1p-1022 && w <= DBL_MAX; }
+
+// --------------------------------------------------------------- wave utils
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+  uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
+  uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+  uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d);
+  uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint64_t o = shfl_xor_u64(v, d);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane) {
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t o = shfl_up_u64(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t lds_load_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_min(uint64_t* keys, uint32_t l, uint64_t key) {
+  if (key < lds_load_u64(&keys[l])) atomicMin((unsigned long long*)&keys[l], (unsigned long long)key);
+}
+
+// ---------------------------------------------------------------- set state
+struct ChainEntry {
+  uint32_t p;
+  uint32_t i;     // next point index
+  uint64_t tacc;  // ProbMinHash1 fixed-point accumulator through point i-1
+};
+
+struct Shared {
+  uint64_t red_u[16];
+  double red_d[16];
+  uint64_t kmax;
+  uint32_t qhead, qtail;
+  uint32_t item;
+  uint32_t bad;
+};
+
+// Per-round view of one set, kept in registers.
+struct Round {
+  const uint64_t* ids;
+  const double* w;
+  uint32_t n, m, imax;
+  uint64_t K0;     // seed hash
+  double T, Tprev; // generate points below T; points below Tprev were handled
+};
+
+template <int NW>
+__device__ uint64_t block_max_keys(const uint64_t* keys, uint32_t m, Shared& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint64_t v = 0;
+  for (uint32_t k = tid; k < m; k += NW * 64) {
+    uint64_t x = keys[k];
+    v = x > v ? x : v;
+  }
+  v = wave_max_u64(v);
+  if (lane == 0) sm.red_u[wv] = v;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t r = sm.red_u[0];
+    for (int i = 1; i < NW; ++i) r = sm.red_u[i] > r ? sm.red_u[i] : r;
+    sm.kmax = r;
+  }
+  __syncthreads();
+  return sm.kmax;
+}
+
+__device__ __forceinline__ uint64_t wave_max_keys(const uint64_t* keys, uint32_t m, int lane) {
+  uint64_t v = 0;
+  for (uint32_t k = lane; k < m; k += 64) {
+    uint64_t x = lds_load_u64(&keys[k]);
+    v = x > v ? x : v;
+  }
+  return wave_max_u64(v);
+}
+
+__device__ __forceinline__ void push_chain(Shared& sm, ChainEntry* q, uint32_t p, uint32_t i, uint64_t tacc) {
+  uint32_t slot = atomicAdd(&sm.qtail, 1u);
+  q[slot] = ChainEntry{p, i, tacc};
+}
+
+// ------------------------------------------------------------- lane mode
+// Returns after the element's points below R.T are applied, or after pushing
+// the element to the chain queue.
+template <int V>
+__device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uint32_t p, double winv,
+                                          uint64_t K, uint64_t kmax, uint64_t* keys, Shared& sm,
+                                          ChainEntry* q, int budget) {
+  const Tables& t = A.t;
+  const uint32_t m = R.m;
+  if constexpr (V == 1) {
+    uint64_t tacc = 0;
+    uint32_t i = 1;
+    for (int step = 0;; ++step) {
+      if (step == budget) {
+        push_chain(sm, q, p, i, tacc);
+        return;
+      }
+      uint64_t pb = pbase(K, i);
+      tacc += (uint64_t)(exp1(mix64(pb)) * 0x1p32);
+      double x = winv * ((double)tacc * 0x1p-32);
+      if (!(x < R.T)) return;
+      uint64_t key = make_key(x, p);
+      if (key >= kmax) return;
+      if (x >= R.Tprev) lds_min(keys, lemire(pb, m), key);
+      if (i == R.imax) return;
+      ++i;
+    }
+  } else if constexpr (V == 3) {
+    const double lam = t.scal[0], c1 = t.scal[1], c2 = t.scal[2], c3 = t.scal[3];
+    uint32_t i = 1;
+    for (int step = 0;; ++step) {
+      double lb = winv * (double)(i - 1);
+      if (!(lb < R.T)) return;
+      if (make_key(lb, p) >= kmax) return;
+      if (step == budget) {
+        push_chain(sm, q, p, i, 0);
+        return;
+      }
+      uint64_t pb = pbase(K, i);
+      double x = lb + winv * trunc_exp(pb, lam, c1, c2, c3, t.expm1c);
+      uint64_t key = make_key(x, p);
+      if (x >= R.Tprev && key < kmax) lds_min(keys, lemire(pb, m), key);
+      if (i == R.imax) return;
+      ++i;
+    }
+  } else {
+    // ProbMinHash2/4: the first kFyLaneSteps Fisher-Yates steps with the
+    // touched slots kept in registers; longer streams restart in chain mode.
+    uint32_t jj[kFyLaneSteps], vv[kFyLaneSteps];
+    uint64_t tacc = 0;
+#pragma unroll
+    for (uint32_t step = 0; step < kFyLaneSteps; ++step) {
+      const uint32_t i = step + 1;
+      if (i > m) return;
+      uint64_t pb = pbase(K, i);
+      double x;
+      if constexpr (V == 2) {
+        tacc += (uint64_t)((t.beta[i] * exp1(mix64(pb))) * 0x1p32);
+        x = winv * ((double)tacc * 0x1p-32);
+        if (!(x < R.T)) return;
+        if (make_key(x, p) >= kmax) return;
+      } else {
+        double lb = winv * t.gam[i - 1];
+        if (!(lb < R.T)) return;
+        if (make_key(lb, p) >= kmax) return;
+        if (i < m)
+          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
+        else
+          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(mix64(pb)));
+      }
+      // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
+      uint32_t j = (i - 1) + lemire(pb, m - i + 1);
+      uint32_t l = j, v = i - 1;
+#pragma unroll
+      for (uint32_t s = 0; s < step; ++s) {
+        if (jj[s] == j) l = vv[s];
+        if (jj[s] == i - 1) v = vv[s];
+      }
+      jj[step] = j;
+      vv[step] = v;
+      uint64_t key = make_key(x, p);
+      if (x >= R.Tprev && key < kmax) lds_min(keys, l, key);
+      if (i == m) return;
+    }
+    push_chain(sm, q, p, 1, 0);
+  }
+}
+
+// ------------------------------------------------------------ chain mode
+// One wavefront runs one element's stream, 64 consecutive points per step.
+template <int V>
+__device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint64_t kmax_round,
+                           uint64_t* keys, uint16_t* g) {
+  const Tables& t = A.t;
+  const int lane = threadIdx.x & 63;
+  const uint32_t m = R.m;
+  const uint32_t p = e.p;
+  const double winv = 1.0 / R.w[p];
+  const uint64_t K = mix64(R.ids[p] ^ R.K0);
+  const uint32_t end = (V == 2 || V == 4) ? m : R.imax;
+  uint64_t kmax = wave_max_keys(keys, m, lane);
+  kmax = kmax < kmax_round ? kmax : kmax_round;
+  uint32_t i0 = e.i;
+  uint64_t tacc = e.tacc;
+  if constexpr (V == 2 || V == 4) {
+    i0 = 1;
+    tacc = 0;
+    for (uint32_t k = lane; k < m; k += 64) g[k] = (uint16_t)k;
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (uint32_t tile = 0;; ++tile) {
+    const uint32_t i = i0 + (uint32_t)lane;
+    const bool valid = i <= end;
+    const uint64_t pb = pbase(K, i);
+    double x = 0.0;
+    uint64_t key = kEmptyKey;
+    bool stop;
+    uint64_t tl = 0;
+    if constexpr (V == 1 || V == 2) {
+      uint64_t d = 0;
+      if (valid) {
+        double E = exp1(mix64(pb));
+        if constexpr (V == 2) E = t.beta[i] * E;
+        d = (uint64_t)(E * 0x1p32);
+      }
+      tl = tacc + wave_incl_scan_u64(d, lane);
+      x = winv * ((double)tl * 0x1p-32);
+      key = make_key(x, p);
+      stop = !valid || !(x < R.T) || key >= kmax;
+    } else if constexpr (V == 3) {
+      double lb = winv * (double)(i - 1);
+      stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
+      if (!stop) {
+        x = lb + winv * trunc_exp(pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        key = make_key(x, p);
+      }
+    } else {
+      stop = !valid;
+      if (valid) {
+        double lb = winv * t.gam[i - 1];
+        stop = !(lb < R.T) || make_key(lb, p) >= kmax;
+      }
+      if (!stop) {
+        if (i < m)
+          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
+        else
+          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(mix64(pb)));
+        key = make_key(x, p);
+      }
+    }
+    const uint64_t stopmask = __ballot(stop);
+    const int first = stopmask ? __builtin_ctzll(stopmask) : 64;
+    const bool active = lane < first;
+    const bool apply = active && x >= R.Tprev && key < kmax;
+    uint32_t label = 0;
+    if constexpr (V == 1 || V == 3) {
+      if (apply) label = lemire(pb, m);
+    } else {
+      // 64 Fisher-Yates steps at once.  Step L (point i0+L) consumes position
+      // P = i-1 and draws slot j >= P; its label is g[j] and it writes the old
+      // g[P] into slot j.  Dependencies inside the tile are resolved by finding,
+      // for each step, the latest earlier step that wrote its slot or position.
+      const int P = (int)i - 1;
+      const int j = active ? P + (int)lemire(pb, m - i + 1) : -1;
+      int lastJ = -1, lastP = -1;
+      bool later = false;
+      for (int s = 0; s < 64; ++s) {
+        const int js = __builtin_amdgcn_readlane(j, s);
+        if (s < lane) {
+          if (js == j) lastJ = s;
+          if (js == P) lastP = s;
+        } else if (s > lane && js == j) {
+          later = true;
+        }
+      }
+      const int gj = active ? (int)g[j] : 0;
+      const int gp = active ? (int)g[P] : 0;
+      int v = gp, ptr = lastP;  // value step L writes = g[P] at step L
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        const int src = ptr >= 0 ? ptr : lane;
+        const int vv = __shfl(v, src);
+        const int pp = __shfl(ptr, src);
+        if (ptr >= 0) {
+          v = vv;
+          ptr = pp;
+        }
+      }
+      const int fromJ = __shfl(v, lastJ >= 0 ? lastJ : lane);
+      label = (uint32_t)(lastJ >= 0 ? fromJ : gj);
+      __builtin_amdgcn_wave_barrier();
+      if (first == 64 && active && !later) g[j] = (uint16_t)v;
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (apply) lds_min(keys, label, key);
+    if (first < 64) break;
+    if constexpr (V == 1 || V == 2) tacc = shfl_u64(tl, 63);
+    i0 += 64;
+    if ((tile & 7) == 7) {
+      uint64_t km = wave_max_keys(keys, m, lane);
+      kmax = km < kmax ? km : kmax;
+    }
+  }
+}
+
+template <int V, int NW>
+__device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t kmax_round, uint64_t* keys,
+                           ChainEntry* q, uint16_t* fy, Shared& sm) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint16_t* g = fy ? fy + (size_t)wv * R.m : nullptr;
+  for (;;) {
+    uint32_t e = 0;
+    if (lane == 0) e = atomicAdd(&sm.qhead, 1u);
+    e = (uint32_t)__shfl((int)e, 0);
+    if (e >= sm.qtail) break;
+    chain_elem<V>(A, R, q[e], kmax_round, keys, g);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sm.qhead = 0;
+    sm.qtail = 0;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------- one set
+template <int V, int NW>
+__device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
+                            uint16_t* fy, Shared& sm) {
+  constexpr int BS = NW * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t m = A.m;
+  const uint64_t a = A.off[set], b = A.off[set + 1];
+  const uint64_t n64 = b - a;
+  Round R;
+  R.ids = A.ids + a;
+  R.w = A.w + a;
+  R.n = (uint32_t)(n64 > kMaxSet ? 0 : n64);
+  R.m = m;
+  R.imax = A.imax;
+  R.K0 = A.seedhash;
+  if (n64 > kMaxSet && tid == 0) atomicOr(A.status, kStatusSetTooLarge);
+
+  for (uint32_t k = tid; k < m; k += BS) keys[k] = kEmptyKey;
+  // total weight (first threshold) and weight validation
+  double ws = 0.0;
+  bool bad = false;
+  for (uint32_t p = tid; p < R.n; p += BS) {
+    double w = R.w[p];
+    if (weight_ok(w)) ws += w;
+    else if (w != 0.0) bad = true;
+  }
+  ws = wave_sum_f64(ws);
+  if (lane == 0) sm.red_d[wv] = ws;
+  if (bad) atomicOr(A.status, kStatusWeight);
+  if (tid == 0) {
+    sm.qhead = 0;
+    sm.qtail = 0;
+  }
+  __syncthreads();
+  double W = 0.0;
+  for (int i = 0; i < NW; ++i) W += sm.red_d[i];
+
+  if (W > 0.0) {
+    double T = (double)m * (log((double)m) + A.c0) / W;
+    double Tprev = 0.0;
+    uint64_t kmax_round = kEmptyKey;
+    for (int round = 0;; ++round) {
+      const bool last = round + 1 >= A.max_rounds || !(T < DBL_MAX) || !(T > 0.0);
+      R.T = last ? __longlong_as_double(0x7FF0000000000000ll) : T;
+      R.Tprev = Tprev;
+      const uint32_t batch = kEpt * BS;
+      uint64_t kmax = kmax_round;
+      for (uint32_t base = 0, nb = 0; base < R.n; base += batch, ++nb) {
+#pragma unroll
+        for (uint32_t k = 0; k < kEpt; ++k) {
+          const uint32_t p = base + k * BS + tid;
+          if (p >= R.n) break;
+          const double w = R.w[p];
+          if (!weight_ok(w)) continue;
+          const double winv = 1.0 / w;
+          const uint64_t K = mix64(R.ids[p] ^ R.K0);
+          if (w * R.T > A.chain_expect) {
+            push_chain(sm, q, p, 1, 0);
+            continue;
+          }
+          lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
+        }
+        __syncthreads();
+        const uint32_t qt = sm.qtail;  // read by every thread before anyone pushes again
+        __syncthreads();
+        const bool flush = qt + batch > qcap;
+        if (flush) chain_pass<V, NW>(A, R, kmax, keys, q, fy, sm);
+        if (flush || (nb % (uint32_t)A.kmax_refresh) == (uint32_t)A.kmax_refresh - 1) {
+          uint64_t km = block_max_keys<NW>(keys, m, sm);
+          kmax = km < kmax ? km : kmax;
+        }
+      }
+      __syncthreads();
+      chain_pass<V, NW>(A, R, kmax, keys, q, fy, sm);
+      const uint64_t K = block_max_keys<NW>(keys, m, sm);
+      if (last || K < make_key(R.T, 0)) break;
+      Tprev = R.T;
+      T = R.T * A.grow;
+      kmax_round = K;
+    }
+  }
+  __syncthreads();
+  // epilogue: keys -> (position, value, id)
+  const uint64_t o = set * (uint64_t)m;
+  for (uint32_t k = tid; k < m; k += BS) {
+    const uint64_t key = keys[k];
+    if (A.out_keys) A.out_keys[o + k] = key;
+    const bool empty = key == kEmptyKey;
+    const uint32_t pos = (uint32_t)(key & kPosMask);
+    if (A.out_idx) A.out_idx[o + k] = empty ? 0xFFFFFFFFu : pos;
+    if (A.out_val) A.out_val[o + k] = empty ? __longlong_as_double(0x7FF0000000000000ll)
+                                            : __longlong_as_double((long long)(key & ~kPosMask));
+    if (A.out_id) A.out_id[o + k] = empty ? 0ull : R.ids[pos];
+  }
+  __syncthreads();
+}
+
+template <int V, int NW>
+__device__ __forceinline__ void carve(uint64_t*& keys, ChainEntry*& q, uint32_t& qcap, uint16_t*& fy,
+                                      uint32_t m) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  keys = reinterpret_cast<uint64_t*>(dyn);
+  q = reinterpret_cast<ChainEntry*>(dyn + (size_t)m * 8);
+  qcap = 2 * kEpt * NW * 64;
+  fy = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(dyn + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry))
+                          : nullptr;
+}
+
+template <int V, int NW>
+__global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
+  __shared__ Shared sm;
+  uint64_t* keys;
+  ChainEntry* q;
+  uint32_t qcap;
+  uint16_t* fy;
+  carve<V, NW>(keys, q, qcap, fy, A.m);
+  for (;;) {
+    if (threadIdx.x == 0) sm.item = atomicAdd(A.counter, 1u);
+    __syncthreads();
+    const uint32_t item = sm.item;
+    __syncthreads();
+    if (item >= A.num_items) break;
+    process_set<V, NW>(A, A.order ? A.order[item] : item, keys, q, qcap, fy, sm);
+  }
+}
+
+template <int V, int NW>
+__global__ __launch_bounds__(NW * 64) void k_hash_one(HashArgs A, uint64_t set) {
+  __shared__ Shared sm;
+  uint64_t* keys;
+  ChainEntry* q;
+  uint32_t qcap;
+  uint16_t* fy;
+  carve<V, NW>(keys, q, qcap, fy, A.m);
+  process_set<V, NW>(A, set, keys, q, qcap, fy, sm);
+}
+
+// ------------------------------------------------------ heavy-first order
+// One workgroup: counting sort of the sets by size class (bit length of n),
+// largest class first; also resets the persistent work counter.
+__global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t num_sets, uint32_t* order,
+                                                uint32_t* counter, uint32_t* status) {
+  __shared__ uint32_t cnt[24];
+  __shared__ uint32_t pos[24];
+  const int tid = threadIdx.x;
+  if (tid < 24) cnt[tid] = 0;
+  __syncthreads();
+  for (uint64_t s = tid; s < num_sets; s += blockDim.x) {
+    const uint64_t n = off[s + 1] - off[s];
+    const uint32_t c = n > kMaxSet ? 23u : (n ? 64u - (uint32_t)__builtin_clzll(n) : 0u);
+    atomicAdd(&cnt[c], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int c = 23; c >= 0; --c) {
+      pos[c] = acc;
+      acc += cnt[c];
+    }
+    *counter = 0;
+    if (cnt[23]) atomicOr(status, kStatusSetTooLarge);
+  }
+  __syncthreads();
+  for (uint64_t s = tid; s < num_sets; s += blockDim.x) {
+    const uint64_t n = off[s + 1] - off[s];
+    const uint32_t c = n > kMaxSet ? 23u : (n ? 64u - (uint32_t)__builtin_clzll(n) : 0u);
+    order[atomicAdd(&pos[c], 1u)] = (uint32_t)s;
+  }
+}
+
+// ---------------------------------------------------------- constant tables
+__global__ void k_init_tables(int variant, uint32_t m, Tables t) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    t.expm1c[0] = 1.0;
+    for (int k = 1; k <= 18; ++k) t.expm1c[k] = t.expm1c[k - 1] / (double)k;
+  }
+  if (variant == 2 && i <= m) t.beta[i] = i == 0 ? 0.0 : (double)m / (double)(m - i + 1);
+  if (variant == 3 && i == 0) {
+    const double a = 1.0 / (double)(m - 1);
+    const double lam = spec_log1p(a);
+    t.scal[0] = lam;
+    t.scal[1] = a / lam;
+    t.scal[2] = spec_log1p(1.0 / (double)(2 * m - 1)) / lam;
+    t.scal[3] = (1.0 / (double)m) / lam;
+  }
+  if (variant == 4 && i < m) {
+    const double lam1 = spec_log1p(1.0 / (double)(m - 1));
+    if (i == 0) {
+      t.lam[0] = t.c1[0] = t.c2[0] = t.c3[0] = 0.0;
+      t.gam[0] = 0.0;
+      t.dgam[0] = 0.0;
+      t.scal[4] = 1.0 / lam1;
+    } else {
+      const double a = 1.0 / (double)(m - i);
+      const double l = spec_log1p(a);
+      t.lam[i] = l;
+      t.c1[i] = a / l;
+      t.c2[i] = spec_log1p(1.0 / (double)(2 * (m - i) + 1)) / l;
+      t.c3[i] = (1.0 / (double)(m - i + 1)) / l;
+      const double gi = spec_log1p((double)i / (double)(m - i)) / lam1;
+      const double gp = i == 1 ? 0.0 : spec_log1p((double)(i - 1) / (double)(m - i + 1)) / lam1;
+      t.gam[i] = gi;
+      t.dgam[i] = gi - gp;
+    }
+  }
+}
+
+// ------------------------------------------------------------- estimation
+// counts[pair] = #{k : idA[k] == idB[k], both components non-empty}
+__global__ __launch_bounds__(256) void k_estimate(const uint64_t* idA, const uint32_t* idxA,
+                                                  const uint64_t* idB, const uint32_t* idxB, uint32_t m,
+                                                  uint32_t* counts) {
+  __shared__ uint32_t red[4];
+  const uint64_t pr = blockIdx.x;
+  const uint64_t o = pr * m;
+  uint32_t c = 0;
+  for (uint32_t k = threadIdx.x; k < m; k += 256)
+    c += (idA[o + k] == idB[o + k] && idxA[o + k] != 0xFFFFFFFFu && idxB[o + k] != 0xFFFFFFFFu) ? 1u : 0u;
+  for (int d = 32; d >= 1; d >>= 1) c += (uint32_t)__shfl_xor((int)c, d);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[pr] = red[0] + red[1] + red[2] + red[3];
+}
+
+// All-pairs equal-component counts over k signatures of m 32-bit fingerprints
+// (fingerprint 0 marks an empty component and never matches).  64x64 pair
+// tile per workgroup, 16 components staged in LDS per step, 4x4 pairs per
+// thread.
+constexpr int kApTile = 64, kApK = 16;
+__global__ __launch_bounds__(256) void k_allpairs(const uint32_t* fp, uint32_t k, uint32_t m,
+                                                  uint16_t* counts) {
+  __shared__ uint32_t sa[kApK][kApTile + 1];
+  __shared__ uint32_t sb[kApK][kApTile + 1];
+  const uint32_t bi = blockIdx.y * kApTile, bj = blockIdx.x * kApTile;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  uint32_t acc[4][4] = {};
+  for (uint32_t c0 = 0; c0 < m; c0 += kApK) {
+    for (int e = threadIdx.x; e < kApK * kApTile; e += 256) {
+      const int r = e / kApK, c = e % kApK;
+      const uint32_t cc = c0 + c;
+      sa[c][r] = (bi + r < k && cc < m) ? fp[(uint64_t)(bi + r) * m + cc] : 0u;
+      sb[c][r] = (bj + r < k && cc < m) ? fp[(uint64_t)(bj + r) * m + cc] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kApK; ++c) {
+      uint32_t av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = sa[c][ty * 4 + u];
+        bv[u] = sb[c][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += (av[u] == bv[v] && av[u] != 0u) ? 1u : 0u;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t r = bi + ty * 4 + u, c = bj + tx * 4 + v;
+      if (r < k && c < k) counts[(uint64_t)r * k + c] = (uint16_t)(acc[u][v] > 65535u ? 65535u : acc[u][v]);
+    }
+}
+
+// --------------------------------------------------------- debug primitives
+// what: 0 log(x), 1 log1p(x), 2 expm1(x), 3 Exp(1) of word u, 4 mix64(u),
+// 5 truncated exponential of (K = u, point k+1) with PMH3 constants,
+// 6 Lemire(m) of (K = u, point k+1), 7 ProbMinHash1 spacing of (K = u, k+1)
+__global__ void k_debug(int what, const double* in, const uint64_t* in_u, double* out, uint64_t* out_u,
+                        uint64_t n, uint32_t m, Tables t) {
+  const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  switch (what) {
+    case 0: out[k] = spec_log(in[k]); break;
+    case 1: out[k] = spec_log1p(in[k]); break;
+    case 2: out[k] = spec_expm1(in[k], t.expm1c); break;
+    case 3: out[k] = exp1(in_u[k]); break;
+    case 4: out_u[k] = mix64(in_u[k]); break;
+    case 5: out[k] = trunc_exp(pbase(in_u[k], (uint32_t)k + 1), t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c); break;
+    case 6: out_u[k] = lemire(pbase(in_u[k], (uint32_t)k + 1), m); break;
+    case 7: out_u[k] = (uint64_t)(exp1(mix64(pbase(in_u[k], (uint32_t)k + 1))) * 0x1p32); break;
+    default: break;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+size_t lds_bytes(int variant, uint32_t m, int waves) {
+  const size_t qcap = 2 * kEpt * (size_t)waves * 64;
+  size_t b = (size_t)m * 8 + qcap * sizeof(ChainEntry);
+  if (variant == 2 || variant == 4) b += (size_t)waves * m * 2;
+  return b;
+}
+
+size_t lds_static_bytes() {
+  return sizeof(Shared) + 64;  // the per-workgroup static block (k_hash_*) plus alignment slack
+}
+
+template <int V, int NW>
+static hipError_t launch_hash_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_hash_persistent<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
+  return hipGetLastError();
+}
+template <int V, int NW>
+static hipError_t launch_one_t(const HashArgs& a, uint64_t set, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_hash_one<V, NW>), dim3(1), dim3(NW * 64), lds, s, a, set);
+  return hipGetLastError();
+}
+template <int V, int NW>
+static hipError_t occ_t(size_t lds, int* out) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)k_hash_persistent<V, NW>, NW * 64, lds);
+}
+
+#define PMH_DISPATCH(FN, ...)                                       \
+  switch (variant * 16 + waves) {                                   \
+    case 16 + 1: return FN<1, 1>(__VA_ARGS__);                      \
+    case 16 + 2: return FN<1, 2>(__VA_ARGS__);                      \
+    case 16 + 4: return FN<1, 4>(__VA_ARGS__);                      \
+    case 32 + 1: return FN<2, 1>(__VA_ARGS__);                      \
+    case 32 + 2: return FN<2, 2>(__VA_ARGS__);                      \
+    case 32 + 4: return FN<2, 4>(__VA_ARGS__);                      \
+    case 48 + 1: return FN<3, 1>(__VA_ARGS__);                      \
+    case 48 + 2: return FN<3, 2>(__VA_ARGS__);                      \
+    case 48 + 4: return FN<3, 4>(__VA_ARGS__);                      \
+    case 64 + 1: return FN<4, 1>(__VA_ARGS__);                      \
+    case 64 + 2: return FN<4, 2>(__VA_ARGS__);                      \
+    case 64 + 4: return FN<4, 4>(__VA_ARGS__);                      \
+    default: return hipErrorInvalidValue;                           \
+  }
+
+hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size_t lds, hipStream_t s) {
+  PMH_DISPATCH(launch_hash_t, a, grid, lds, s)
+}
+hipError_t launch_hash_one(int variant, const HashArgs& a, uint64_t set, int waves, size_t lds, hipStream_t s) {
+  PMH_DISPATCH(launch_one_t, a, set, lds, s)
+}
+hipError_t occupancy(int variant, int waves, size_t lds, int* blocks_per_cu) {
+  PMH_DISPATCH(occ_t, lds, blocks_per_cu)
+}
+
+hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t* order, uint32_t* counter,
+                        uint32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, off, num_sets, order, counter, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_tables(int variant, uint32_t m, Tables t, hipStream_t s) {
+  const uint32_t n = m + 1;
+  hipLaunchKernelGGL(k_init_tables, dim3((n + 255) / 256), dim3(256), 0, s, variant, m, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB, const uint32_t* idxB,
+                           uint32_t m, uint64_t pairs, uint32_t* counts, hipStream_t s) {
+  if (pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_estimate, dim3((uint32_t)pairs), dim3(256), 0, s, idA, idxA, idB, idxB, m, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_allpairs(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  const uint32_t tiles = (k + kApTile - 1) / kApTile;
+  hipLaunchKernelGGL(k_allpairs, dim3(tiles, tiles), dim3(256), 0, s, fp, k, m, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_eval(int what, const double* in, const uint64_t* in_u, double* out, uint64_t* out_u,
+                             uint64_t n, uint32_t m, int variant, Tables t, hipStream_t s) {
+  (void)variant;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, what, in, in_u, out, out_u, n,
+                     m, t);
+  return hipGetLastError();
+}
+
+}  // namespace pmh

@@ -1,0 +1,387 @@
+// Host runtime of libpmh.so: contexts, constant tables, launches, HIP-graph
+// replay, estimation and the C ABI declared in include/pmh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/pmh.h"
+#include "pmh_internal.h"
+#include "pmh_runtime.h"
+
+using namespace pmh;
+
+namespace pmh {
+
+uint64_t host_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint32_t imax_for(uint32_t m) {
+  uint32_t bits = 0;
+  for (uint32_t v = m; v; v >>= 1) ++bits;
+  return 6u * m * bits + 64u;  // stream cap of ProbMinHash1/3
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  (void)hipGetDevice(&prev_);
+  if (prev_ != dev) (void)hipSetDevice(dev);
+  dev_ = dev;
+}
+DeviceGuard::~DeviceGuard() {
+  if (prev_ != dev_) (void)hipSetDevice(prev_);
+}
+
+size_t lds_limit_bytes(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return 65536 - lds_static_bytes();
+  return p.sharedMemPerBlock - lds_static_bytes();  // budget for the dynamic part
+}
+
+int effective_waves(const pmh_ctx* c) {
+  int w = c->tune.waves;
+  if (w != 1 && w != 2 && w != 4) w = 4;
+  while (w > 1 && lds_bytes(c->variant, c->m, w) > c->lds_limit) w >>= 1;
+  return w;
+}
+
+int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets) {
+  if (wb->cap >= num_sets && wb->order) return PMH_OK;
+  uint64_t cap = std::max<uint64_t>(num_sets, 1024);
+  cap = std::max<uint64_t>(cap, wb->cap * 2);
+  if (wb->order) (void)hipFree(wb->order);
+  wb->order = nullptr;
+  wb->cap = 0;
+  if (hipMalloc(&wb->order, cap * sizeof(uint32_t)) != hipSuccess) return PMH_ERR_OOM;
+  wb->cap = cap;
+  if (!wb->counter && hipMalloc(&wb->counter, sizeof(uint32_t) * 4) != hipSuccess) return PMH_ERR_OOM;
+  (void)c;
+  return PMH_OK;
+}
+
+HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off,
+                   uint64_t num_sets, uint32_t* idx, double* val, uint64_t* id, uint64_t* keys,
+                   const WorkBuf* wb) {
+  HashArgs a{};
+  a.ids = ids;
+  a.w = w;
+  a.off = off;
+  a.num_sets = num_sets;
+  a.out_idx = idx;
+  a.out_val = val;
+  a.out_id = id;
+  a.out_keys = keys;
+  a.seedhash = c->seedhash;
+  a.m = c->m;
+  a.imax = imax_for(c->m);
+  a.t = c->t;
+  a.c0 = c->tune.c0;
+  a.grow = c->tune.grow;
+  a.chain_expect = c->tune.chain_expect;
+  a.max_rounds = c->tune.max_rounds;
+  a.lane_budget = c->tune.lane_budget;
+  a.kmax_refresh = c->tune.kmax_refresh;
+  a.status = c->status;
+  a.order = wb ? wb->order : nullptr;
+  a.counter = wb ? wb->counter : nullptr;
+  a.num_items = (uint32_t)num_sets;
+  a.points = nullptr;
+  return a;
+}
+
+int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s) {
+  if (a.num_sets == 0) return PMH_OK;
+  const int waves = effective_waves(c);
+  const size_t lds = lds_bytes(c->variant, c->m, waves);
+  int per_cu = c->tune.blocks_per_cu;
+  if (per_cu <= 0) {
+    if (occupancy(c->variant, waves, lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+  }
+  uint64_t grid = (uint64_t)c->num_cu * (uint64_t)per_cu;
+  grid = std::min<uint64_t>(grid, a.num_sets);
+  if (launch_order(a.off, a.num_sets, wb->order, wb->counter, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (launch_hash(c->variant, a, waves, (int)grid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
+  return PMH_OK;
+}
+
+}  // namespace pmh
+
+// ============================================================== C ABI
+extern "C" {
+
+const char* pmh_status_str(int st) {
+  switch (st) {
+    case PMH_OK: return "ok";
+    case PMH_ERR_ARG: return "invalid argument";
+    case PMH_ERR_M_RANGE: return "signature size m out of range";
+    case PMH_ERR_VARIANT_M: return "ProbMinHash3/4 need m >= 2";
+    case PMH_ERR_WEIGHT: return "negative, NaN, infinite or subnormal weight";
+    case PMH_ERR_SET_TOO_LARGE: return "set with more than 2^20 elements";
+    case PMH_ERR_DEVICE: return "HIP runtime error";
+    case PMH_ERR_OOM: return "out of memory";
+    case PMH_ERR_BUSY: return "serving queue full";
+    case PMH_ERR_NOT_READY: return "request not finished";
+    default: return "unknown status";
+  }
+}
+
+uint32_t pmh_max_m(int variant) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t lim = lds_limit_bytes(dev);
+  uint32_t m = kMaxM;
+  while (m > 1 && lds_bytes(variant, m, 1) > lim) m -= 64;
+  return m;
+}
+
+int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
+  if (!out) return PMH_ERR_ARG;
+  *out = nullptr;
+  if (variant < 1 || variant > 4) return PMH_ERR_ARG;
+  if (m < 1 || m > kMaxM) return PMH_ERR_M_RANGE;
+  if ((variant == 3 || variant == 4) && m < 2) return PMH_ERR_VARIANT_M;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PMH_ERR_DEVICE;
+  const size_t lim = lds_limit_bytes(dev);
+  if (lds_bytes(variant, m, 1) > lim) return PMH_ERR_M_RANGE;
+  pmh_ctx* c = new (std::nothrow) pmh_ctx();
+  if (!c) return PMH_ERR_OOM;
+  c->seed = seed;
+  c->seedhash = host_mix64(seed);
+  c->m = m;
+  c->variant = variant;
+  c->device = dev;
+  c->lds_limit = lim;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete c;
+    return PMH_ERR_DEVICE;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  // constant tables: 7 arrays of m+1 doubles + expm1 (19) + scalars (8)
+  const size_t nd = 7 * (size_t)(m + 1) + 19 + 8;
+  if (hipMalloc(&c->table_mem, nd * sizeof(double)) != hipSuccess) {
+    delete c;
+    return PMH_ERR_OOM;
+  }
+  double* d = (double*)c->table_mem;
+  c->t.beta = d;
+  c->t.lam = d + 1 * (size_t)(m + 1);
+  c->t.c1 = d + 2 * (size_t)(m + 1);
+  c->t.c2 = d + 3 * (size_t)(m + 1);
+  c->t.c3 = d + 4 * (size_t)(m + 1);
+  c->t.gam = d + 5 * (size_t)(m + 1);
+  c->t.dgam = d + 6 * (size_t)(m + 1);
+  c->t.expm1c = d + 7 * (size_t)(m + 1);
+  c->t.scal = c->t.expm1c + 19;
+  int rc = PMH_OK;
+  if (hipMemset(c->table_mem, 0, nd * sizeof(double)) != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (!rc && hipMalloc(&c->status, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_OOM;
+  if (!rc && hipMemset(c->status, 0, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (!rc && launch_init_tables(variant, m, c->t, nullptr) != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (!rc && hipDeviceSynchronize() != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (!rc && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (rc) {
+    pmh_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return PMH_OK;
+}
+
+void pmh_destroy(pmh_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->work.order) (void)hipFree(c->work.order);
+  if (c->work.counter) (void)hipFree(c->work.counter);
+  if (c->table_mem) (void)hipFree(c->table_mem);
+  if (c->status) (void)hipFree(c->status);
+  delete c;
+}
+
+static int check_hash_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off,
+                           uint64_t num_sets) {
+  if (!c) return PMH_ERR_ARG;
+  if (num_sets == 0) return PMH_OK;
+  if (!off || !ids || !w) return PMH_ERR_ARG;
+  if (num_sets >= 0xFFFFFFFFull) return PMH_ERR_ARG;
+  return PMH_OK;
+}
+
+int pmh_hash_sets(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
+                  uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, void* stream) {
+  int rc = check_hash_args(c, ids, w, off, num_sets);
+  if (rc || num_sets == 0) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  rc = ensure_work(c, &c->work, num_sets);
+  if (rc) return rc;
+  HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
+  return enqueue_batched(c, a, &c->work, (hipStream_t)stream);
+}
+
+int pmh_hash_sets_plain(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off,
+                        uint64_t num_sets, uint32_t* idx, double* val, uint64_t* id, uint64_t* keys,
+                        void* stream) {
+  int rc = check_hash_args(c, ids, w, off, num_sets);
+  if (rc || num_sets == 0) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, nullptr);
+  const int waves = effective_waves(c);
+  const size_t lds = lds_bytes(c->variant, c->m, waves);
+  for (uint64_t s = 0; s < num_sets; ++s)
+    if (launch_hash_one(c->variant, a, s, waves, lds, (hipStream_t)stream) != hipSuccess) return PMH_ERR_DEVICE;
+  return PMH_OK;
+}
+
+int pmh_hash_sets_graph(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off,
+                        uint64_t num_sets, uint32_t* idx, double* val, uint64_t* id, uint64_t* keys,
+                        void* stream) {
+  int rc = check_hash_args(c, ids, w, off, num_sets);
+  if (rc || num_sets == 0) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  const GraphKey key{ids, w, off, num_sets, idx, val, id, keys, c->tune_version};
+  if (!c->gexec || !(key == c->gkey)) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    rc = ensure_work(c, &c->work, num_sets);
+    if (rc) return rc;
+    HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PMH_ERR_DEVICE;
+    rc = enqueue_batched(c, a, &c->work, c->cap_stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess || !gr) return PMH_ERR_DEVICE;
+    if (hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(gr);
+      return PMH_ERR_DEVICE;
+    }
+    c->graph = gr;
+    c->gkey = key;
+  }
+  return hipGraphLaunch(c->gexec, (hipStream_t)stream) == hipSuccess ? PMH_OK : PMH_ERR_DEVICE;
+}
+
+int pmh_get_status(pmh_ctx* c, void* stream) {
+  if (!c) return PMH_ERR_ARG;
+  DeviceGuard g(c->device);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PMH_ERR_DEVICE;
+  uint32_t st = 0;
+  if (hipMemcpy(&st, c->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return PMH_ERR_DEVICE;
+  if (st && hipMemset(c->status, 0, sizeof(uint32_t)) != hipSuccess) return PMH_ERR_DEVICE;
+  if (st & kStatusWeight) return PMH_ERR_WEIGHT;
+  if (st & kStatusSetTooLarge) return PMH_ERR_SET_TOO_LARGE;
+  return PMH_OK;
+}
+
+int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
+  if (!c || !t) return PMH_ERR_ARG;
+  if (!(t->grow > 1.0) || t->max_rounds < 1 || t->lane_budget < 1 || t->kmax_refresh < 1 ||
+      (t->waves != 1 && t->waves != 2 && t->waves != 4) || t->blocks_per_cu < 0 || !(t->c0 > -100.0) ||
+      !(t->chain_expect >= 0.0))
+    return PMH_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->tune.c0 = t->c0;
+  c->tune.grow = t->grow;
+  c->tune.max_rounds = t->max_rounds;
+  c->tune.chain_expect = t->chain_expect;
+  c->tune.lane_budget = t->lane_budget;
+  c->tune.waves = t->waves;
+  c->tune.kmax_refresh = t->kmax_refresh;
+  c->tune.blocks_per_cu = t->blocks_per_cu;
+  c->tune_version++;
+  return PMH_OK;
+}
+
+int pmh_get_tuning(const pmh_ctx* c, pmh_tuning* t) {
+  if (!c || !t) return PMH_ERR_ARG;
+  t->c0 = c->tune.c0;
+  t->grow = c->tune.grow;
+  t->max_rounds = c->tune.max_rounds;
+  t->chain_expect = c->tune.chain_expect;
+  t->lane_budget = c->tune.lane_budget;
+  t->waves = c->tune.waves;
+  t->kmax_refresh = c->tune.kmax_refresh;
+  t->blocks_per_cu = c->tune.blocks_per_cu;
+  return PMH_OK;
+}
+
+int pmh_estimate(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB, const uint32_t* idxB,
+                 uint32_t m, double* out) {
+  if (!idA || !idxA || !idB || !idxB || !out || m == 0) return PMH_ERR_ARG;
+  uint64_t eq = 0;
+  for (uint32_t k = 0; k < m; ++k)
+    eq += (idA[k] == idB[k] && idxA[k] != 0xFFFFFFFFu && idxB[k] != 0xFFFFFFFFu) ? 1u : 0u;
+  *out = (double)eq / (double)m;
+  return PMH_OK;
+}
+
+int pmh_estimate_pairs(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB, const uint32_t* idxB,
+                       uint32_t m, uint64_t pairs, uint32_t* counts, void* stream) {
+  if (pairs == 0) return PMH_OK;
+  if (!idA || !idxA || !idB || !idxB || !counts || m == 0 || pairs > 0x7FFFFFFFull) return PMH_ERR_ARG;
+  return launch_estimate(idA, idxA, idB, idxB, m, pairs, counts, (hipStream_t)stream) == hipSuccess
+             ? PMH_OK
+             : PMH_ERR_DEVICE;
+}
+
+int pmh_allpairs_counts(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts, void* stream) {
+  if (k == 0) return PMH_OK;
+  if (!fp || !counts || m == 0) return PMH_ERR_ARG;
+  return launch_allpairs(fp, k, m, counts, (hipStream_t)stream) == hipSuccess ? PMH_OK : PMH_ERR_DEVICE;
+}
+
+int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
+  if (!c || !out) return PMH_ERR_ARG;
+  DeviceGuard g(c->device);
+  const double* src = nullptr;
+  size_t avail = 0;
+  switch (which) {
+    case 0: src = c->t.beta; avail = c->m + 1; break;
+    case 1: src = c->t.lam; avail = c->m; break;
+    case 2: src = c->t.c1; avail = c->m; break;
+    case 3: src = c->t.c2; avail = c->m; break;
+    case 4: src = c->t.c3; avail = c->m; break;
+    case 5: src = c->t.gam; avail = c->m; break;
+    case 6: src = c->t.dgam; avail = c->m; break;
+    case 7: src = c->t.scal; avail = 8; break;
+    case 8: src = c->t.expm1c; avail = 19; break;
+    default: return PMH_ERR_ARG;
+  }
+  if (count > avail) return PMH_ERR_ARG;
+  if (hipDeviceSynchronize() != hipSuccess) return PMH_ERR_DEVICE;
+  return hipMemcpy(out, src, count * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess ? PMH_OK : PMH_ERR_DEVICE;
+}
+
+int pmh_debug_eval(pmh_ctx* c, int what, const double* in, const uint64_t* in_u, double* out, uint64_t* out_u,
+                   uint64_t n, void* stream) {
+  if (!c || what < 0 || what > 7) return PMH_ERR_ARG;
+  const bool uses_u = what >= 3;
+  const bool out_is_u = what == 4 || what == 6 || what == 7;
+  if ((uses_u && !in_u) || (!uses_u && !in) || (out_is_u && !out_u) || (!out_is_u && !out)) return PMH_ERR_ARG;
+  if (what == 5 && c->variant != 3) return PMH_ERR_ARG;
+  DeviceGuard g(c->device);
+  return launch_debug_eval(what, in, in_u, out, out_u, n, c->m, c->variant, c->t, (hipStream_t)stream) == hipSuccess
+             ? PMH_OK
+             : PMH_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Host-side runtime structures shared by pmh_runtime.cpp, pmh_autotune.cpp and
+// pmh_server.cpp.  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "pmh_internal.h"
+
+namespace pmh {
+
+// Per-call device scratch: the heavy-first work list and the persistent
+// grid's work counter.
+struct WorkBuf {
+  uint32_t* order = nullptr;
+  uint32_t* counter = nullptr;
+  uint64_t cap = 0;
+};
+
+struct GraphKey {
+  const void* ids;
+  const void* w;
+  const void* off;
+  uint64_t num_sets;
+  const void* idx;
+  const void* val;
+  const void* id;
+  const void* keys;
+  uint64_t tune_version;
+  bool operator==(const GraphKey& o) const {
+    return ids == o.ids && w == o.w && off == o.off && num_sets == o.num_sets && idx == o.idx && val == o.val &&
+           id == o.id && keys == o.keys && tune_version == o.tune_version;
+  }
+};
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+
+ private:
+  int prev_ = 0, dev_ = 0;
+};
+
+uint64_t host_mix64(uint64_t z);
+uint32_t imax_for(uint32_t m);
+size_t lds_limit_bytes(int device);
+
+}  // namespace pmh
+
+struct pmh_ctx {
+  uint64_t seed = 0, seedhash = 0;
+  uint32_t m = 0;
+  int variant = 1;
+  int device = 0;
+  int num_cu = 1;
+  size_t lds_limit = 65536;
+  void* table_mem = nullptr;
+  pmh::Tables t{};
+  uint32_t* status = nullptr;
+  pmh::WorkBuf work;
+  pmh::Tuning tune;
+  uint64_t tune_version = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  pmh::GraphKey gkey{};
+  std::mutex mu;
+};
+
+namespace pmh {
+int effective_waves(const pmh_ctx* c);
+int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets);
+HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
+                   uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, const WorkBuf* wb);
+int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s);
+}  // namespace pmh

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Integer/byte work (keys, positions, ids) must be bit-exact; the floating-point
+stream primitives must be bit-exact too, because every signature index is an
+argmin over them (the tolerance is zero by construction of the reading).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1911_00675_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+SEED = 0x5EED
+
+
+@pytest.fixture(scope="module")
+def pmh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1911_00675_amd import pmh as P
+    P.lib()
+    O.build()
+    return P
+
+
+def _keys(ctx, b, mode="batched"):
+    sig = ctx.hash_sets(_dev(b.ids), _dev(b.weights), _dev(b.offsets), mode=mode)
+    st = ctx.status()
+    return sig, st
+
+
+def _dev(a):
+    from paper_1911_00675_amd import pmh as P
+    return P.to_device(a)
+
+
+def _host(sig):
+    return (sig.keys.cpu().numpy().view(np.uint64), sig.idx.cpu().numpy().view(np.uint32),
+            sig.val.cpu().numpy(), sig.id.cpu().numpy().view(np.uint64))
+
+
+# ----------------------------------------------------------------- primitives
+def test_primitives_bitwise(pmh):
+    print("primitives: log/log1p/expm1/exp1/mix64/trunc-exp/lemire/spacing", flush=True)
+    m = 256
+    ctx = pmh.Context(SEED, m, 3)
+    rng = np.random.default_rng(1)
+    ks = rng.integers(1, 2**53, size=20000)
+    u = ks.astype(np.float64) * 2.0 ** -53
+    u[:3] = [1.0, 2.0 ** -53, 0.5]
+    got = ctx.debug_eval(0, u)
+    want = np.array([O.spec_log(x) for x in u])
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    x = np.concatenate([1.0 / np.arange(1, 5000), np.exp(rng.uniform(-30, 12, 5000))])
+    assert np.array_equal(ctx.debug_eval(1, x).view(np.uint64),
+                          np.array([O.spec_log1p(v) for v in x]).view(np.uint64))
+    t = np.linspace(0, np.log(2), 3001)
+    assert np.array_equal(ctx.debug_eval(2, t).view(np.uint64),
+                          np.array([O.spec_expm1(v) for v in t]).view(np.uint64))
+    words = rng.integers(0, 2**63, size=20000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    words[:2] = [np.uint64(0), np.uint64(2**64 - 1)]
+    assert np.array_equal(ctx.debug_eval(3, words).view(np.uint64),
+                          np.array([O.exp1_of_word(int(wd)) for wd in words]).view(np.uint64))
+    assert np.array_equal(ctx.debug_eval(4, words), np.array([O.mix64(int(wd)) for wd in words], dtype=np.uint64))
+    lam, c1, c2, c3 = O.constants(3, m)[:4]
+    Ks = rng.integers(0, 2**63, size=20000, dtype=np.uint64)
+    te = ctx.debug_eval(5, Ks)
+    want = np.array([O.trunc_exp(int(K), k + 1, lam, c1, c2, c3) for k, K in enumerate(Ks)])
+    assert np.array_equal(te.view(np.uint64), want.view(np.uint64))
+    lab = ctx.debug_eval(6, Ks)
+    assert np.array_equal(lab, np.array([O.lemire(int(K), k + 1, m) for k, K in enumerate(Ks)], dtype=np.uint64))
+    sp = ctx.debug_eval(7, Ks)
+    want = np.array([int(O.exp1_of_word(O.word(int(K), k + 1, 0)) * 2.0 ** 32) for k, K in enumerate(Ks)],
+                    dtype=np.uint64)
+    assert np.array_equal(sp, want)
+    ctx.close()
+
+
+@pytest.mark.parametrize("m", [2, 3, 64, 1000, 4096])
+def test_constant_tables_bitwise(pmh, m):
+    print(f"tables m={m}", flush=True)
+    c2 = pmh.Context(SEED, m, 2)
+    beta = c2.table(0, m + 1)
+    assert all(beta[i] == O.constants(2, m, i)[0] for i in range(1, m + 1))
+    c2.close()
+    c3 = pmh.Context(SEED, m, 3)
+    sc = c3.table(7, 8)
+    assert np.array_equal(sc[:4].view(np.uint64), O.constants(3, m)[:4].view(np.uint64))
+    c3.close()
+    c4 = pmh.Context(SEED, m, 4)
+    lam, c1, cc2, c3_, gam, dgam = (c4.table(w, m) for w in (1, 2, 3, 4, 5, 6))
+    delta = c4.table(7, 8)[4]
+    for i in range(1, m):
+        ref = O.constants(4, m, i)
+        got = np.array([lam[i], c1[i], cc2[i], c3_[i], gam[i], dgam[i], delta])
+        assert np.array_equal(got.view(np.uint64), ref[:7].view(np.uint64)), i
+    c4.close()
+
+
+# ----------------------------------------------------------------- signatures
+VARIANT_M = [(v, m) for v in (1, 2, 3, 4) for m in (1, 2, 3, 64, 100, 1024) if not (v >= 3 and m == 1)]
+
+
+@pytest.mark.parametrize("variant,m", VARIANT_M)
+def test_random_batches_bit_exact(pmh, variant, m):
+    """Ragged batches (sizes 0..600, several weight laws): keys, positions,
+    values and ids equal the oracle's in the batched, plain and graph forms."""
+    print(f"random batch PMH{variant} m={m}", flush=True)
+    ctx = pmh.Context(SEED, m, variant)
+    for law, seed in (("exp", 1), ("pareto", 2), ("wide", 3), ("ones", 4)):
+        b = W.random_sets(100 * variant + seed + m, 40, 0, 600, law)
+        want = O.sign_batch(variant, SEED, m, b.ids, b.weights, b.offsets, nthreads=8)
+        for mode in ("batched", "plain", "graph"):
+            sig, st = _keys(ctx, b, mode)
+            assert st == pmh.PMH_OK
+            keys, idx, val, ids = _host(sig)
+            assert np.array_equal(keys, want), (law, mode)
+        for s in range(b.num_sets):
+            si, _ = b.set(s)
+            ri, rv, rid = O.decode(want[s], si)
+            assert np.array_equal(idx[s], ri) and np.array_equal(ids[s], rid)
+            assert np.array_equal(val[s].view(np.uint64), rv.view(np.uint64))
+    ctx.close()
+
+
+def test_plain_pairs_workload(pmh):
+    """1,000 sets x 100 elements, m = 256, ProbMinHash1, one launch per set:
+    bit-exact, and the 200 sharing pairs obey the collision law."""
+    print("plain_pairs workload", flush=True)
+    from scipy import stats
+    b = W.plain_pairs()
+    ctx = pmh.Context(SEED, 256, 1)
+    sig, st = _keys(ctx, b, "plain")
+    assert st == pmh.PMH_OK
+    keys, idx, val, ids = _host(sig)
+    want = O.sign_batch(1, SEED, 256, b.ids, b.weights, b.offsets, nthreads=8)
+    assert np.array_equal(keys, want)
+    num, var, outside = 0.0, 0.0, 0
+    for sa, sb in b.meta["pairs"]:
+        ia, wa = b.set(sa)
+        ib, wb = b.set(sb)
+        J = O.jp_sorted(ia, wa, ib, wb)
+        c = round(pmh.estimate(ids[sa], idx[sa], ids[sb], idx[sb]) * 256)
+        num += c - 256 * J
+        var += 256 * J * (1 - J)
+        outside += not (stats.binom.ppf(0.005, 256, J) <= c <= stats.binom.ppf(0.995, 256, J))
+    assert abs(num / np.sqrt(var)) <= 2.576 and outside <= 6
+    ctx.close()
+
+
+def test_edge_cases(pmh):
+    """Empty sets, single elements, zero weights, invalid weights (skipped and
+    reported), extreme weights."""
+    print("edge cases", flush=True)
+    m = 64
+    sizes = [0, 1, 0, 2, 1, 5, 0]
+    rng = np.random.default_rng(9)
+    N = sum(sizes)
+    ids = rng.integers(0, 2**64 - 1, size=N, dtype=np.uint64)
+    w = rng.exponential(size=N) + 0.01
+    w[3] = 0.0
+    w[5] = 1e-300
+    w[6] = 1e300
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    b = W.Batch(ids, w, off)
+    for v in (1, 2, 3, 4):
+        ctx = pmh.Context(SEED, m, v)
+        sig, st = _keys(ctx, b)
+        assert st == pmh.PMH_OK
+        want = O.sign_batch(v, SEED, m, ids, w, off)
+        assert np.array_equal(_host(sig)[0], want)
+        assert (_host(sig)[1][0] == 0xFFFFFFFF).all() and np.isinf(_host(sig)[2][0]).all()
+        # invalid weights: skipped like zeros, reported once
+        wb = w.copy()
+        wb[4] = -1.0
+        wb[7] = np.nan
+        wb[8] = 1e-310
+        sig, st = _keys(ctx, W.Batch(ids, wb, off))
+        assert st == pmh.PMH_ERR_WEIGHT
+        wz = wb.copy()
+        wz[[4, 7, 8]] = 0.0
+        assert np.array_equal(_host(sig)[0], O.sign_batch(v, SEED, m, ids, wz, off))
+        assert ctx.status() == pmh.PMH_OK  # cleared after reading
+        ctx.close()
+
+
+def test_oversize_set_reported(pmh):
+    print("oversize set", flush=True)
+    n = (1 << 20) + 1
+    rng = np.random.default_rng(10)
+    b = W.Batch(rng.integers(0, 2**64 - 1, size=n + 3, dtype=np.uint64), np.ones(n + 3),
+                np.array([0, 3, n + 3], dtype=np.uint64))
+    ctx = pmh.Context(SEED, 32, 1)
+    sig, st = _keys(ctx, b)
+    assert st == pmh.PMH_ERR_SET_TOO_LARGE
+    keys = _host(sig)[0]
+    assert np.array_equal(keys[0], O.sign(1, SEED, 32, b.ids[:3], b.weights[:3]))
+    assert (keys[1] == O.EMPTY).all()
+    ctx.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_schedule_invariance(pmh, variant):
+    """The signature does not depend on the schedule: thresholds, rounds, lane
+    or chain mode, waves per workgroup, grid size (reading: exact minimum over
+    all points, Sec. 2 stop rule as pure pruning)."""
+    print(f"schedule invariance PMH{variant}", flush=True)
+    m = 256
+    b = W.random_sets(500 + variant, 60, 0, 2000, "pareto")
+    want = O.sign_batch(variant, SEED, m, b.ids, b.weights, b.offsets, nthreads=8)
+    ctx = pmh.Context(SEED, m, variant)
+    configs = [dict(), dict(c0=-6.0, grow=1.3, max_rounds=12), dict(max_rounds=1), dict(chain_expect=0.0),
+               dict(chain_expect=1e9, lane_budget=1000000), dict(lane_budget=1), dict(waves=1), dict(waves=2),
+               dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0)]
+    for cfg in configs:
+        ctx.set_tuning(**cfg)
+        sig, st = _keys(ctx, b)
+        assert st == pmh.PMH_OK
+        assert np.array_equal(_host(sig)[0], want), cfg
+        ctx.set_tuning(c0=3.0, grow=2.0, max_rounds=4, chain_expect=12.0, lane_budget=8, waves=4,
+                       blocks_per_cu=0, kmax_refresh=8)
+    ctx.close()
+
+
+def test_alone_and_in_a_mix(pmh):
+    """A set's signature is the same alone, in any batch, at any position."""
+    print("alone vs mix", flush=True)
+    b = W.random_sets(77, 100, 1, 3000, "exp")
+    ctx = pmh.Context(SEED, 512, 3)
+    full = _host(_keys(ctx, b)[0])[0]
+    rng = np.random.default_rng(5)
+    for s in rng.choice(b.num_sets, 8, replace=False):
+        alone = _host(_keys(ctx, b.subset([s]))[0])[0][0]
+        assert np.array_equal(alone, full[s])
+        order = rng.permutation(b.num_sets)
+        mixed = _host(_keys(ctx, b.subset(order))[0])[0]
+        assert np.array_equal(mixed[np.where(order == s)[0][0]], full[s])
+    ctx.close()
