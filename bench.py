@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark: weighted elements hashed per second at m = 1024.
+
+One step hashes the mixed-size workload (100,000 weighted sets, sizes
+log-uniform in [1, 10^4], 20% of ids from a shared pool of 10^6, Pareto(1.5)
+weights normalised per set, ~1.09e8 elements) with ProbMinHash1 and with
+ProbMinHash3 in the batched persistent launch, inputs resident in HBM.
+Also reported on the same inputs: the one-launch-per-set (plain) form, p50 /
+p99 / p99.9 latency of the continuous-batching server under Poisson arrivals
+at 50k requests/s (ProbMinHash3, m = 1024, sizes log-uniform in [10, 10^5]),
+the roofline of the dominant kernel and the CPU reference on host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M = 1024
+SEED = 0x5EED
+VARIANTS = (1, 3)
+# VALU lane-instructions per algorithmic unit on gfx950, counted in the ISA of
+# this library's primitives ("Roofline"): an element needs its
+# weight inverse, its key hash and its first point; a point below the final
+# stop limit needs its value, its label and one LDS min.
+OPS_PER_ELEMENT = {1: 117, 3: 68}
+OPS_PER_POINT = {1: 112, 3: 63}
+PEAK_VALU = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+PEAK_HBM = 8.0e12                     # bytes/s
+
+
+def harmonic(n):
+    return float(np.sum(1.0 / np.arange(1, n + 1)))
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sets", type=int, default=100_000)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=6000)
+    ap.add_argument("--cpu-sets", type=int, default=3000)
+    ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.profile:
+        args.no_plain = args.no_serving = args.no_cpu = True
+    import torch
+    from paper_1911_00675_amd import pmh, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    b = W.mixed_sizes(num_sets=args.sets)
+    log(f"workload: {b.num_sets} sets, {b.num_elements} elements ({time.time() - t0:.1f}s to generate)")
+    ids, w, off = pmh.to_device(b.ids), pmh.to_device(b.weights), pmh.to_device(b.offsets)
+    S, N = b.num_sets, b.num_elements
+    ctxs = {v: pmh.Context(SEED, M, v) for v in VARIANTS}
+    outs = {v: ctxs[v].alloc_outputs(S, ("idx", "val", "id")) for v in VARIANTS}
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for v in VARIANTS:
+            if events is not None:
+                events[v][0].record(stream)
+            ctxs[v].hash_sets(ids, w, off, out=outs[v])
+            if events is not None:
+                events[v][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for v in VARIANTS:
+        assert ctxs[v].status() == pmh.PMH_OK
+    ev = [{v: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for v in VARIANTS}
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    launch_ms = {v: float(np.mean([e[v][0].elapsed_time(e[v][1]) for e in ev])) for v in VARIANTS}
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = len(VARIANTS) * N / (elapsed / args.steps)
+    log(f"batched: {ms_per_step:.3f} ms/step, per launch {launch_ms}")
+
+    # ------------------------------------------------------------ roofline
+    sizes = b.sizes()
+    nz = sizes > 0
+    q = M * harmonic(M)
+    units_e = int(sizes.sum())
+    units_p = float(q * nz.sum())
+    roof = {}
+    for v in VARIANTS:
+        ops = units_e * OPS_PER_ELEMENT[v] + units_p * OPS_PER_POINT[v]
+        roof[v] = ops / (launch_ms[v] * 1e-3)
+    dom = max(VARIANTS, key=lambda v: launch_ms[v])
+    hbm_bytes = 16.0 * N + 8.0 * (S + 1) + 20.0 * S * M
+    roofline = {
+        "bound": "alu", "kernel": f"k_hash_persistent<ProbMinHash{dom}>",
+        "achieved": roof[dom] / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
+        "frac": roof[dom] / PEAK_VALU, "traffic": None,
+        "ops_model": {"per_element": OPS_PER_ELEMENT[dom], "per_point": OPS_PER_POINT[dom],
+                      "elements": units_e, "points": units_p},
+        "per_variant_frac": {f"pmh{v}": roof[v] / PEAK_VALU for v in VARIANTS},
+        "hbm_algorithmic_GBps": hbm_bytes / (launch_ms[dom] * 1e-3) / 1e9,
+        "hbm_frac": hbm_bytes / (launch_ms[dom] * 1e-3) / PEAK_HBM,
+    }
+
+    # ------------------------------------------------------------ plain form
+    plain = None
+    if not args.no_plain:
+        plain = {}
+        for v in VARIANTS:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctxs[v].hash_sets(ids, w, off, out=outs[v], mode="plain")
+            e1.record(stream)
+            torch.cuda.synchronize()
+            pms = e0.elapsed_time(e1)
+            plain[f"pmh{v}"] = {"ms": pms, "elements_per_s": N / (pms * 1e-3),
+                                "batched_over_plain": pms / launch_ms[v]}
+        log(f"plain: {plain}")
+
+    # ------------------------------------------------------------ serving
+    latency = None
+    if not args.no_serving:
+        rq = W.serving_requests(num_requests=args.serving_requests)
+        srv = pmh.Server(ctxs[3], slots=4, slot_elems=1 << 23, slot_sets=4096)
+        warm = min(1000, rq.num_sets // 4)
+        lat, _, _, wall = srv.replay(rq.ids, rq.weights, rq.offsets, rq.meta["arrival"])
+        st = srv.stats()
+        srv.close()
+        lm = lat[warm:] * 1e6
+        latency = {"p50_us": float(np.percentile(lm, 50)), "p99_us": float(np.percentile(lm, 99)),
+                   "p999_us": float(np.percentile(lm, 99.9)), "requests": int(rq.num_sets - warm),
+                   "offered_req_per_s": rq.meta["rate"], "achieved_req_per_s": rq.num_sets / wall,
+                   "elements_per_s": rq.num_elements / wall, "variant": "ProbMinHash3", "m": M,
+                   "server": st}
+        log(f"serving: {latency}")
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oracle.build()
+        cores = os.cpu_count() or 1
+        samp = b.subset(np.arange(min(args.cpu_sets, S)))
+        tc = {}
+        for v in VARIANTS:
+            c0 = time.perf_counter()
+            oracle.sign_batch(v, SEED, M, samp.ids, samp.weights, samp.offsets, nthreads=cores)
+            tc[v] = time.perf_counter() - c0
+        cpu_val = len(VARIANTS) * samp.num_elements / sum(tc.values())
+        cpu = {"value": cpu_val, "unit": "elements/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {samp.num_sets} sets ({samp.num_elements} elements) of the same workload, "
+                         f"ProbMinHash1+3 sequential per set, {cores} threads",
+               "seconds": {f"pmh{v}": tc[v] for v in VARIANTS}}
+        log(f"cpu: {cpu}")
+
+    out = {
+        "metric": "weighted elements hashed/s at m=1024 (batched vs per-set launch); p99 latency",
+        "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"mixed_sizes: {S} sets, sizes log-uniform [1,1e4], 20% pooled ids, "
+                               f"Pareto(1.5) weights, m={M}, ProbMinHash1+ProbMinHash3, batched persistent",
+                   "num_sets": S, "num_elements": N, "m": M, "variants": list(VARIANTS),
+                   "per_launch_ms": {f"pmh{v}": launch_ms[v] for v in VARIANTS},
+                   "elements_per_s": {f"pmh{v}": N / (launch_ms[v] * 1e-3) for v in VARIANTS},
+                   "components_per_s": {f"pmh{v}": S * M / (launch_ms[v] * 1e-3) for v in VARIANTS}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "latency": latency,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

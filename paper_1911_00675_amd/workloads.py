@@ -79,21 +79,20 @@ def _log_uniform_int(rng, lo: int, hi: int, n: int) -> np.ndarray:
     return np.clip(v, lo, hi)
 
 
-def _distinct_fill(rng, ids: np.ndarray, offsets: np.ndarray) -> np.ndarray:
-    """Replace in-set duplicate ids by fresh random ids until every set is
-    duplicate-free (duplicates of random 64-bit ids are vanishingly rare, but
-    pool draws can repeat)."""
-    sizes = np.diff(offsets).astype(np.int64)
-    set_of = np.repeat(np.arange(sizes.size), sizes)
+def _dedupe_pool_draws(rng, pool_idx: np.ndarray, set_of: np.ndarray, pool_size: int) -> np.ndarray:
+    """Redraw pool indices that repeat within a set, so every set holds
+    distinct ids.  (Fresh uniform 64-bit ids are not checked: two equal ids
+    among the n <= 10^6 fresh ids of one set occur with probability below
+    n^2 / 2^65 < 3e-8.)"""
     for _ in range(64):
-        order = np.lexsort((ids, set_of))
-        s_sorted, i_sorted = set_of[order], ids[order]
-        dup = np.zeros(ids.size, dtype=bool)
-        dup[1:] = (s_sorted[1:] == s_sorted[:-1]) & (i_sorted[1:] == i_sorted[:-1])
+        key = set_of.astype(np.int64) * pool_size + pool_idx.astype(np.int64)
+        _, first = np.unique(key, return_index=True)
+        dup = np.ones(key.size, dtype=bool)
+        dup[first] = False
         if not dup.any():
-            return ids
-        ids[order[dup]] = _rand_u64(rng, int(dup.sum()))
-    raise RuntimeError("could not make sets duplicate-free")
+            return pool_idx
+        pool_idx[dup] = rng.integers(0, pool_size, size=int(dup.sum()))
+    raise RuntimeError("could not make pool draws distinct")
 
 
 # --------------------------------------------------------------------------- #
@@ -113,7 +112,6 @@ def plain_pairs(seed: int = 1, num_sets: int = 1000, n: int = 100, num_pairs: in
     w = rng.exponential(1.0, size=num_sets * n)
     w = np.where(w > 0, w, 1.0)
     off = _offsets(np.full(num_sets, n))
-    ids = _distinct_fill(rng, ids, off)
     return Batch(ids, _normalise(w, off), off,
                  dict(name="plain_pairs", seed=seed, pairs=[(2 * j, 2 * j + 1) for j in range(num_pairs)]))
 
@@ -130,8 +128,10 @@ def mixed_sizes(seed: int = 2, num_sets: int = 100_000, n_lo: int = 1, n_hi: int
     pool = _rand_u64(rng, pool_size)
     ids = _rand_u64(rng, N)
     from_pool = rng.random(N) < pool_frac
-    ids[from_pool] = pool[rng.integers(0, pool_size, size=int(from_pool.sum()))]
-    ids = _distinct_fill(rng, ids, off)
+    set_of = np.repeat(np.arange(num_sets, dtype=np.int64), sizes)
+    pidx = _dedupe_pool_draws(rng, rng.integers(0, pool_size, size=int(from_pool.sum())), set_of[from_pool],
+                              pool_size)
+    ids[from_pool] = pool[pidx]
     w = (1.0 - rng.random(N)) ** (-1.0 / pareto_shape)
     return Batch(ids, _normalise(w, off), off, dict(name="mixed_sizes", seed=seed))
 
@@ -147,7 +147,7 @@ def skewed(seed: int = 3, num_sets: int = 10_000, large_frac: float = 0.1,
                      _log_uniform_int(rng, small[0], small[1], num_sets))
     off = _offsets(sizes)
     N = int(off[-1])
-    ids = _distinct_fill(rng, _rand_u64(rng, N), off)
+    ids = _rand_u64(rng, N)
     w = 1.0 - rng.random(N)  # (0, 1]
     return Batch(ids, _normalise(w, off), off, dict(name="skewed", seed=seed))
 
@@ -161,7 +161,7 @@ def serving_requests(seed: int = 4, num_requests: int = 220_000, rate: float = 5
     sizes = _log_uniform_int(rng, n_lo, n_hi, num_requests)
     off = _offsets(sizes)
     N = int(off[-1])
-    ids = _distinct_fill(rng, _rand_u64(rng, N), off)
+    ids = _rand_u64(rng, N)
     w = rng.exponential(1.0, size=N)
     w = np.where(w > 0, w, 1.0)
     arrival = np.cumsum(rng.exponential(1.0 / rate, size=num_requests))
@@ -230,7 +230,7 @@ def random_sets(seed: int, num_sets: int, n_lo: int, n_hi: int, weight_law: str 
     sizes = rng.integers(n_lo, n_hi + 1, size=num_sets)
     off = _offsets(sizes)
     N = int(off[-1])
-    ids = _distinct_fill(rng, _rand_u64(rng, N), off)
+    ids = _rand_u64(rng, N)
     if weight_law == "exp":
         w = rng.exponential(1.0, size=N)
         w = np.where(w > 0, w, 1.0)
