@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--cpu-sets", type=int, default=3000)
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (3 times) to calibrate HBM byte counters")
     return ap.parse_args()
 
 
@@ -106,6 +108,13 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = len(VARIANTS) * N / (elapsed / args.steps)
     log(f"batched: {ms_per_step:.3f} ms/step, per launch {launch_ms}")
+    if args.copy_calibrate:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ------------------------------------------------------------ roofline
     sizes = b.sizes()

@@ -82,6 +82,7 @@ typedef struct {
   int waves;          /* wavefronts per workgroup: 1, 2 or 4 */
   int kmax_refresh;   /* element batches between stop-limit refreshes (>= 1) */
   int blocks_per_cu;  /* persistent grid = CUs * this (0: occupancy limit) */
+  double mini_expect; /* ProbMinHash1/3 elements expecting more points run as 8-lane mini-chains */
 } pmh_tuning;
 
 /* Create a context for (seed, m, variant) on the current device.  variant is

@@ -75,7 +75,8 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
           for (double c0 : {1.0, 2.0, 3.0, 4.0, 6.0}) add([&](Tuning& t) { t.c0 = c0; });
           break;
         case 2:
-          for (double ce : {4.0, 8.0, 12.0, 24.0, 48.0}) add([&](Tuning& t) { t.chain_expect = ce; });
+          for (double ce : {16.0, 32.0, 48.0, 96.0, 192.0}) add([&](Tuning& t) { t.chain_expect = ce; });
+          for (double me : {1.0, 2.0, 3.0, 5.0, 8.0}) add([&](Tuning& t) { t.mini_expect = me; });
           break;
         case 3:
           for (int lb : {2, 4, 8, 16}) add([&](Tuning& t) { t.lane_budget = lb; });
@@ -112,6 +113,7 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
     best_out->waves = best.waves;
     best_out->kmax_refresh = best.kmax_refresh;
     best_out->blocks_per_cu = best.blocks_per_cu;
+    best_out->mini_expect = best.mini_expect;
   }
   return rc;
 }

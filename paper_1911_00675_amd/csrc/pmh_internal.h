@@ -35,11 +35,12 @@ struct Tuning {
   double c0 = 3.0;          // first threshold T0 = m (ln m + c0) / sum(w)
   double grow = 2.0;        // T_{r+1} = grow * T_r
   int max_rounds = 4;       // the last round runs with T = +inf
-  double chain_expect = 12; // elements expecting more points than this go to chain mode
+  double chain_expect = 48; // elements expecting more points than this run as 64-lane chains
   int lane_budget = 8;      // lane-mode steps before an element moves to chain mode
   int waves = 4;            // waves per workgroup
   int kmax_refresh = 8;     // element batches between stop-limit refreshes
   int blocks_per_cu = 0;    // persistent grid = CUs * this (0: occupancy limit)
+  double mini_expect = 3;   // ProbMinHash1/3 elements expecting more points run as 8-lane mini-chains
 };
 
 struct HashArgs {
@@ -55,7 +56,7 @@ struct HashArgs {
   uint32_t m;
   uint32_t imax;
   Tables t;
-  double c0, grow, chain_expect;
+  double c0, grow, chain_expect, mini_expect;
   int max_rounds, lane_budget, kmax_refresh;
   uint32_t* status;          // device status word
   const uint32_t* order;     // work list (set indices), heavy first

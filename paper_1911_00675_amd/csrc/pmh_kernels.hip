@@ -195,16 +195,16 @@ __device__ __forceinline__ void lds_min(uint64_t* keys, uint32_t l, uint64_t key
 struct ChainEntry {
   uint32_t p;
   uint32_t i;     // next point index
-  uint64_t tacc;  // ProbMinHash1 fixed-point accumulator through point i-1
+  uint64_t tacc;  // ProbMinHash1/2 fixed-point accumulator through point i-1
 };
 
 struct Shared {
   uint64_t red_u[16];
   double red_d[16];
-  uint64_t kmax;
-  uint32_t qhead, qtail;
+  uint64_t kmax;          // stop-limit estimate, always >= max_k keys[k]
+  uint32_t qhead, qtail;  // long-chain queue: front of the queue array
+  uint32_t mhead, mtail;  // mini-chain queue: back of the queue array
   uint32_t item;
-  uint32_t bad;
 };
 
 // Per-round view of one set, kept in registers.
@@ -212,9 +212,14 @@ struct Round {
   const uint64_t* ids;
   const double* w;
   uint32_t n, m, imax;
+  uint32_t qcap;
   uint64_t K0;     // seed hash
   double T, Tprev; // generate points below T; points below Tprev were handled
 };
+
+__device__ __forceinline__ uint64_t shared_kmax(Shared& sm) {
+  return __hip_atomic_load(&sm.kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 template <int NW>
 __device__ uint64_t block_max_keys(const uint64_t* keys, uint32_t m, Shared& sm) {
@@ -245,14 +250,20 @@ __device__ __forceinline__ uint64_t wave_max_keys(const uint64_t* keys, uint32_t
   return wave_max_u64(v);
 }
 
-__device__ __forceinline__ void push_chain(Shared& sm, ChainEntry* q, uint32_t p, uint32_t i, uint64_t tacc) {
-  uint32_t slot = atomicAdd(&sm.qtail, 1u);
+// Long streams go to the front of the queue array, medium streams to the back.
+__device__ __forceinline__ void push_long(Shared& sm, ChainEntry* q, uint32_t p, uint32_t i, uint64_t tacc) {
+  const uint32_t slot = atomicAdd(&sm.qtail, 1u);
   q[slot] = ChainEntry{p, i, tacc};
+}
+__device__ __forceinline__ void push_mini(Shared& sm, ChainEntry* q, uint32_t qcap, uint32_t p, uint32_t i,
+                                          uint64_t tacc) {
+  const uint32_t slot = atomicAdd(&sm.mtail, 1u);
+  q[qcap - 1 - slot] = ChainEntry{p, i, tacc};
 }
 
 // ------------------------------------------------------------- lane mode
 // Returns after the element's points below R.T are applied, or after pushing
-// the element to the chain queue.
+// the element to a chain queue.
 template <int V>
 __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uint32_t p, double winv,
                                           uint64_t K, uint64_t kmax, uint64_t* keys, Shared& sm,
@@ -264,14 +275,14 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
     uint32_t i = 1;
     for (int step = 0;; ++step) {
       if (step == budget) {
-        push_chain(sm, q, p, i, tacc);
+        push_mini(sm, q, R.qcap, p, i, tacc);
         return;
       }
-      uint64_t pb = pbase(K, i);
+      const uint64_t pb = pbase(K, i);
       tacc += (uint64_t)(exp1(mix64(pb)) * 0x1p32);
-      double x = winv * ((double)tacc * 0x1p-32);
+      const double x = winv * ((double)tacc * 0x1p-32);
       if (!(x < R.T)) return;
-      uint64_t key = make_key(x, p);
+      const uint64_t key = make_key(x, p);
       if (key >= kmax) return;
       if (x >= R.Tprev) lds_min(keys, lemire(pb, m), key);
       if (i == R.imax) return;
@@ -281,16 +292,16 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
     const double lam = t.scal[0], c1 = t.scal[1], c2 = t.scal[2], c3 = t.scal[3];
     uint32_t i = 1;
     for (int step = 0;; ++step) {
-      double lb = winv * (double)(i - 1);
+      const double lb = winv * (double)(i - 1);
       if (!(lb < R.T)) return;
       if (make_key(lb, p) >= kmax) return;
       if (step == budget) {
-        push_chain(sm, q, p, i, 0);
+        push_mini(sm, q, R.qcap, p, i, 0);
         return;
       }
-      uint64_t pb = pbase(K, i);
-      double x = lb + winv * trunc_exp(pb, lam, c1, c2, c3, t.expm1c);
-      uint64_t key = make_key(x, p);
+      const uint64_t pb = pbase(K, i);
+      const double x = lb + winv * trunc_exp(pb, lam, c1, c2, c3, t.expm1c);
+      const uint64_t key = make_key(x, p);
       if (x >= R.Tprev && key < kmax) lds_min(keys, lemire(pb, m), key);
       if (i == R.imax) return;
       ++i;
@@ -304,7 +315,7 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
     for (uint32_t step = 0; step < kFyLaneSteps; ++step) {
       const uint32_t i = step + 1;
       if (i > m) return;
-      uint64_t pb = pbase(K, i);
+      const uint64_t pb = pbase(K, i);
       double x;
       if constexpr (V == 2) {
         tacc += (uint64_t)((t.beta[i] * exp1(mix64(pb))) * 0x1p32);
@@ -312,7 +323,7 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
         if (!(x < R.T)) return;
         if (make_key(x, p) >= kmax) return;
       } else {
-        double lb = winv * t.gam[i - 1];
+        const double lb = winv * t.gam[i - 1];
         if (!(lb < R.T)) return;
         if (make_key(lb, p) >= kmax) return;
         if (i < m)
@@ -321,7 +332,7 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
           x = winv * (t.gam[m - 1] + t.scal[4] * exp1(mix64(pb)));
       }
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
-      uint32_t j = (i - 1) + lemire(pb, m - i + 1);
+      const uint32_t j = (i - 1) + lemire(pb, m - i + 1);
       uint32_t l = j, v = i - 1;
 #pragma unroll
       for (uint32_t s = 0; s < step; ++s) {
@@ -330,19 +341,19 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
       }
       jj[step] = j;
       vv[step] = v;
-      uint64_t key = make_key(x, p);
+      const uint64_t key = make_key(x, p);
       if (x >= R.Tprev && key < kmax) lds_min(keys, l, key);
       if (i == m) return;
     }
-    push_chain(sm, q, p, 1, 0);
+    push_long(sm, q, p, 1, 0);
   }
 }
 
 // ------------------------------------------------------------ chain mode
 // One wavefront runs one element's stream, 64 consecutive points per step.
 template <int V>
-__device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint64_t kmax_round,
-                           uint64_t* keys, uint16_t* g) {
+__device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint64_t* keys, uint16_t* g,
+                           Shared& sm) {
   const Tables& t = A.t;
   const int lane = threadIdx.x & 63;
   const uint32_t m = R.m;
@@ -350,8 +361,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
   const double winv = 1.0 / R.w[p];
   const uint64_t K = mix64(R.ids[p] ^ R.K0);
   const uint32_t end = (V == 2 || V == 4) ? m : R.imax;
-  uint64_t kmax = wave_max_keys(keys, m, lane);
-  kmax = kmax < kmax_round ? kmax : kmax_round;
+  uint64_t kmax = shared_kmax(sm);
   uint32_t i0 = e.i;
   uint64_t tacc = e.tacc;
   if constexpr (V == 2 || V == 4) {
@@ -360,7 +370,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
     for (uint32_t k = lane; k < m; k += 64) g[k] = (uint16_t)k;
     __builtin_amdgcn_wave_barrier();
   }
-  for (uint32_t tile = 0;; ++tile) {
+  for (uint32_t tile = 1;; ++tile) {
     const uint32_t i = i0 + (uint32_t)lane;
     const bool valid = i <= end;
     const uint64_t pb = pbase(K, i);
@@ -380,7 +390,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
       key = make_key(x, p);
       stop = !valid || !(x < R.T) || key >= kmax;
     } else if constexpr (V == 3) {
-      double lb = winv * (double)(i - 1);
+      const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
         x = lb + winv * trunc_exp(pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
@@ -389,7 +399,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
     } else {
       stop = !valid;
       if (valid) {
-        double lb = winv * t.gam[i - 1];
+        const double lb = winv * t.gam[i - 1];
         stop = !(lb < R.T) || make_key(lb, p) >= kmax;
       }
       if (!stop) {
@@ -448,29 +458,109 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
     if (first < 64) break;
     if constexpr (V == 1 || V == 2) tacc = shfl_u64(tl, 63);
     i0 += 64;
-    if ((tile & 7) == 7) {
-      uint64_t km = wave_max_keys(keys, m, lane);
-      kmax = km < kmax ? km : kmax;
+    if ((tile & 15) == 0) {  // tighten the shared stop limit now and then
+      const uint64_t km = wave_max_keys(keys, m, lane);
+      if (lane == 0 && km < shared_kmax(sm)) atomicMin((unsigned long long*)&sm.kmax, (unsigned long long)km);
+    }
+    const uint64_t ks = shared_kmax(sm);
+    kmax = ks < kmax ? ks : kmax;
+  }
+}
+
+// Mini-chain mode (ProbMinHash1/3): the wave is split into eight 8-lane
+// groups, each running one medium-length stream 8 consecutive points per
+// step and taking the next queued stream as soon as its own ends.
+template <int V>
+__device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, ChainEntry* q, Shared& sm) {
+  const Tables& t = A.t;
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 7, leader = lane & ~7, grp = lane >> 3;
+  const uint32_t m = R.m, end = R.imax;
+  const uint32_t mtail = sm.mtail;
+  bool have = false;
+  uint32_t p = 0, i0 = 1;
+  uint64_t tacc = 0, K = 0;
+  double winv = 0.0;
+  uint64_t kmax = shared_kmax(sm);
+  for (uint32_t step = 0;; ++step) {
+    if (!have) {  // group-uniform
+      uint32_t e = 0;
+      if (j == 0) e = atomicAdd(&sm.mhead, 1u);
+      e = (uint32_t)__shfl((int)e, leader);
+      if (e < mtail) {
+        const ChainEntry ce = q[R.qcap - 1 - e];
+        p = ce.p;
+        i0 = ce.i;
+        tacc = ce.tacc;
+        winv = 1.0 / R.w[p];
+        K = mix64(R.ids[p] ^ R.K0);
+        have = true;
+      }
+    }
+    if (__ballot(have) == 0) break;
+    const uint32_t i = i0 + (uint32_t)j;
+    const bool valid = have && i <= end;
+    const uint64_t pb = pbase(K, i);
+    double x = 0.0;
+    uint64_t key = kEmptyKey, tl = 0;
+    bool stop;
+    if constexpr (V == 1) {
+      uint64_t d = valid ? (uint64_t)(exp1(mix64(pb)) * 0x1p32) : 0;
+      for (int dd = 1; dd < 8; dd <<= 1) {
+        const uint64_t o = shfl_u64(d, lane - dd >= leader ? lane - dd : lane);
+        if (j >= dd) d += o;
+      }
+      tl = tacc + d;
+      x = winv * ((double)tl * 0x1p-32);
+      key = make_key(x, p);
+      stop = !valid || !(x < R.T) || key >= kmax;
+    } else {
+      const double lb = winv * (double)(i - 1);
+      stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
+      if (!stop) {
+        x = lb + winv * trunc_exp(pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        key = make_key(x, p);
+      }
+    }
+    const uint64_t smask = __ballot(stop);
+    const uint32_t bits = (uint32_t)(smask >> (grp * 8)) & 0xFFu;
+    const int first = __builtin_ctz(bits | 0x100u);
+    const bool apply = have && j < first && x >= R.Tprev && key < kmax;
+    if (apply) lds_min(keys, lemire(pb, m), key);
+    const uint64_t tlast = shfl_u64(tl, leader + 7);
+    if (have) {
+      if (first < 8) {
+        have = false;
+      } else {
+        i0 += 8;
+        tacc = tlast;
+      }
+    }
+    if ((step & 3) == 3) {
+      const uint64_t ks = shared_kmax(sm);
+      kmax = ks < kmax ? ks : kmax;
     }
   }
 }
 
 template <int V, int NW>
-__device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t kmax_round, uint64_t* keys,
-                           ChainEntry* q, uint16_t* fy, Shared& sm) {
+__device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, ChainEntry* q, uint16_t* fy,
+                           Shared& sm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint16_t* g = fy ? fy + (size_t)wv * R.m : nullptr;
-  for (;;) {
+  const uint32_t qtail = sm.qtail;
+  for (;;) {  // long streams first
     uint32_t e = 0;
     if (lane == 0) e = atomicAdd(&sm.qhead, 1u);
     e = (uint32_t)__shfl((int)e, 0);
-    if (e >= sm.qtail) break;
-    chain_elem<V>(A, R, q[e], kmax_round, keys, g);
+    if (e >= qtail) break;
+    chain_elem<V>(A, R, q[e], keys, g, sm);
   }
+  if constexpr (V == 1 || V == 3) mini_pass<V>(A, R, keys, q, sm);
   __syncthreads();
   if (threadIdx.x == 0) {
-    sm.qhead = 0;
-    sm.qtail = 0;
+    sm.qhead = sm.qtail = 0;
+    sm.mhead = sm.mtail = 0;
   }
   __syncthreads();
 }
@@ -490,6 +580,7 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
   R.n = (uint32_t)(n64 > kMaxSet ? 0 : n64);
   R.m = m;
   R.imax = A.imax;
+  R.qcap = qcap;
   R.K0 = A.seedhash;
   if (n64 > kMaxSet && tid == 0) atomicOr(A.status, kStatusSetTooLarge);
 
@@ -498,17 +589,13 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
   double ws = 0.0;
   bool bad = false;
   for (uint32_t p = tid; p < R.n; p += BS) {
-    double w = R.w[p];
+    const double w = R.w[p];
     if (weight_ok(w)) ws += w;
     else if (w != 0.0) bad = true;
   }
   ws = wave_sum_f64(ws);
   if (lane == 0) sm.red_d[wv] = ws;
   if (bad) atomicOr(A.status, kStatusWeight);
-  if (tid == 0) {
-    sm.qhead = 0;
-    sm.qtail = 0;
-  }
   __syncthreads();
   double W = 0.0;
   for (int i = 0; i < NW; ++i) W += sm.red_d[i];
@@ -521,35 +608,43 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
       const bool last = round + 1 >= A.max_rounds || !(T < DBL_MAX) || !(T > 0.0);
       R.T = last ? __longlong_as_double(0x7FF0000000000000ll) : T;
       R.Tprev = Tprev;
+      if (tid == 0) {
+        sm.kmax = kmax_round;
+        sm.qhead = sm.qtail = 0;
+        sm.mhead = sm.mtail = 0;
+      }
+      __syncthreads();
       const uint32_t batch = kEpt * BS;
-      uint64_t kmax = kmax_round;
       for (uint32_t base = 0, nb = 0; base < R.n; base += batch, ++nb) {
+        const uint64_t kmax = shared_kmax(sm);
 #pragma unroll
         for (uint32_t k = 0; k < kEpt; ++k) {
           const uint32_t p = base + k * BS + tid;
           if (p >= R.n) break;
           const double w = R.w[p];
           if (!weight_ok(w)) continue;
-          const double winv = 1.0 / w;
-          const uint64_t K = mix64(R.ids[p] ^ R.K0);
-          if (w * R.T > A.chain_expect) {
-            push_chain(sm, q, p, 1, 0);
+          const double lam = w * R.T;  // expected points below T
+          if (lam > A.chain_expect) {
+            push_long(sm, q, p, 1, 0);
             continue;
           }
+          if ((V == 1 || V == 3) && lam > A.mini_expect) {
+            push_mini(sm, q, qcap, p, 1, 0);
+            continue;
+          }
+          const double winv = 1.0 / w;
+          const uint64_t K = mix64(R.ids[p] ^ R.K0);
           lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
         }
         __syncthreads();
-        const uint32_t qt = sm.qtail;  // read by every thread before anyone pushes again
+        const uint32_t qt = sm.qtail + sm.mtail;  // read by every thread before anyone pushes again
         __syncthreads();
         const bool flush = qt + batch > qcap;
-        if (flush) chain_pass<V, NW>(A, R, kmax, keys, q, fy, sm);
-        if (flush || (nb % (uint32_t)A.kmax_refresh) == (uint32_t)A.kmax_refresh - 1) {
-          uint64_t km = block_max_keys<NW>(keys, m, sm);
-          kmax = km < kmax ? km : kmax;
-        }
+        if (flush) chain_pass<V, NW>(A, R, keys, q, fy, sm);
+        if (flush || (nb % (uint32_t)A.kmax_refresh) == (uint32_t)A.kmax_refresh - 1) block_max_keys<NW>(keys, m, sm);
       }
       __syncthreads();
-      chain_pass<V, NW>(A, R, kmax, keys, q, fy, sm);
+      chain_pass<V, NW>(A, R, keys, q, fy, sm);
       const uint64_t K = block_max_keys<NW>(keys, m, sm);
       if (last || K < make_key(R.T, 0)) break;
       Tprev = R.T;

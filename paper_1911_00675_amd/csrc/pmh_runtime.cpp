@@ -84,6 +84,7 @@ HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const
   a.c0 = c->tune.c0;
   a.grow = c->tune.grow;
   a.chain_expect = c->tune.chain_expect;
+  a.mini_expect = c->tune.mini_expect;
   a.max_rounds = c->tune.max_rounds;
   a.lane_budget = c->tune.lane_budget;
   a.kmax_refresh = c->tune.kmax_refresh;
@@ -296,7 +297,7 @@ int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
   if (!c || !t) return PMH_ERR_ARG;
   if (!(t->grow > 1.0) || t->max_rounds < 1 || t->lane_budget < 1 || t->kmax_refresh < 1 ||
       (t->waves != 1 && t->waves != 2 && t->waves != 4) || t->blocks_per_cu < 0 || !(t->c0 > -100.0) ||
-      !(t->chain_expect >= 0.0))
+      !(t->chain_expect >= 0.0) || !(t->mini_expect >= 0.0))
     return PMH_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->mu);
   c->tune.c0 = t->c0;
@@ -307,6 +308,7 @@ int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
   c->tune.waves = t->waves;
   c->tune.kmax_refresh = t->kmax_refresh;
   c->tune.blocks_per_cu = t->blocks_per_cu;
+  c->tune.mini_expect = t->mini_expect;
   c->tune_version++;
   return PMH_OK;
 }
@@ -321,6 +323,7 @@ int pmh_get_tuning(const pmh_ctx* c, pmh_tuning* t) {
   t->waves = c->tune.waves;
   t->kmax_refresh = c->tune.kmax_refresh;
   t->blocks_per_cu = c->tune.blocks_per_cu;
+  t->mini_expect = c->tune.mini_expect;
   return PMH_OK;
 }
 

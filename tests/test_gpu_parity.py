@@ -210,16 +210,17 @@ def test_schedule_invariance(pmh, variant):
     b = W.random_sets(500 + variant, 60, 0, 2000, "pareto")
     want = O.sign_batch(variant, SEED, m, b.ids, b.weights, b.offsets, nthreads=8)
     ctx = pmh.Context(SEED, m, variant)
+    default = ctx.get_tuning().as_dict()
     configs = [dict(), dict(c0=-6.0, grow=1.3, max_rounds=12), dict(max_rounds=1), dict(chain_expect=0.0),
-               dict(chain_expect=1e9, lane_budget=1000000), dict(lane_budget=1), dict(waves=1), dict(waves=2),
+               dict(chain_expect=1e9, mini_expect=1e9, lane_budget=1000000), dict(lane_budget=1),
+               dict(mini_expect=0.0), dict(mini_expect=0.0, chain_expect=1e9), dict(waves=1), dict(waves=2),
                dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0)]
     for cfg in configs:
         ctx.set_tuning(**cfg)
         sig, st = _keys(ctx, b)
         assert st == pmh.PMH_OK
         assert np.array_equal(_host(sig)[0], want), cfg
-        ctx.set_tuning(c0=3.0, grow=2.0, max_rounds=4, chain_expect=12.0, lane_budget=8, waves=4,
-                       blocks_per_cu=0, kmax_refresh=8)
+        ctx.set_tuning(**default)
     ctx.close()
 
 
