@@ -68,13 +68,18 @@ static inline uint64_t o_word(uint64_t K, uint64_t i, unsigned t) {
     uint64_t c = (i << 8) | (uint64_t)t;
     return o_mix64(K + (c + 1) * O_PHI);
 }
-/* slots of point i */
-#define O_SLOT_VALUE 0u   /* uniform behind the point value */
-#define O_SLOT_LABEL 1u   /* label draw; Lemire redraws use 2..9 */
-#define O_SLOT_REJ 16u    /* truncated-exponential rejection pairs use 16..79 */
+/* Slots of point i.  Word 0 serves the point twice, drawing only the bits
+ * each use needs (Sec. 3: random bits are consumed economically): its high 32
+ * bits are the uniform behind the point value, its low 32 bits the label draw.
+ * Words 1..8 hold Lemire redraws (low 32 bits); words 16..79 the rejection
+ * pairs of the truncated-exponential sampler (53-bit uniforms). */
+#define O_SLOT_POINT 0u
+#define O_SLOT_REDRAW 1u
+#define O_SLOT_REJ 16u
 
+static inline double o_u32(uint64_t w) { return (double)(w >> 32) * 0x1p-32; }        /* [0,1) */
+static inline double o_upos(uint64_t w) { return (double)((w >> 32) + 1) * 0x1p-32; } /* (0,1] */
 static inline double o_u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }        /* [0,1) */
-static inline double o_upos(uint64_t w) { return (double)((w >> 11) + 1) * 0x1p-53; } /* (0,1] */
 
 /* ------------------------------------------------------------------------ */
 /* Logarithm written from ln x = e ln 2 + 2 atanh((f-1)/(f+1)), x = 2^e f with
@@ -139,16 +144,16 @@ double or_expm1(double t) {
 /* Exp(1) by inversion; 0 - log(u) keeps the result +0 for u = 1. */
 static inline double o_exp1(uint64_t w) { return 0.0 - or_log(o_upos(w)); }
 
-/* Uniform integer in [0, s), Lemire's multiply-and-reject method on the high
- * 32 bits of the label words of point i (at most 8 redraws). */
+/* Uniform integer in [0, s), Lemire's multiply-and-reject method on the low
+ * 32 bits of the point's word, redrawing from words 1..8 (at most 8 redraws). */
 static uint32_t o_lemire(uint64_t K, uint64_t i, uint32_t s) {
-    uint64_t x = o_word(K, i, O_SLOT_LABEL) >> 32;
+    uint64_t x = o_word(K, i, O_SLOT_POINT) & 0xFFFFFFFFULL;
     uint64_t prod = x * (uint64_t)s;
     uint32_t lo = (uint32_t)prod;
     if (lo < s) {
         uint32_t thr = (uint32_t)(0u - s) % s;
         for (unsigned r = 1; lo < thr && r <= 8; ++r) {
-            x = o_word(K, i, O_SLOT_LABEL + r) >> 32;
+            x = o_word(K, i, O_SLOT_REDRAW + r - 1) & 0xFFFFFFFFULL;
             prod = x * (uint64_t)s;
             lo = (uint32_t)prod;
         }
@@ -162,7 +167,7 @@ static uint32_t o_lemire(uint64_t K, uint64_t i, uint32_t s) {
  * c1 = (e^lam - 1)/lam, c2 = log(2/(1+e^-lam))/lam, c3 = (1-e^-lam)/lam.
  * The rejection loop is capped at 32 rounds (Sec. 3 recommends capped loops). */
 static double o_te(uint64_t K, uint64_t i, double lam, double c1, double c2, double c3) {
-    double x = c1 * o_u53(o_word(K, i, O_SLOT_VALUE));
+    double x = c1 * o_u32(o_word(K, i, O_SLOT_POINT));
     if (x < 1.0) return x;
     for (unsigned it = 0; it < 32; ++it) {
         x = o_u53(o_word(K, i, O_SLOT_REJ + 2 * it));
@@ -272,7 +277,7 @@ static int o_params_init(o_params *P, int variant, uint32_t m) {
  * accumulate the exponential spacings in 64-bit fixed point (2^-32 units) and
  * round once: x_i = winv * (T_i 2^-32), T_i = T_{i-1} + floor(s_i 2^32). */
 static inline uint64_t o_spacing(const o_params *P, uint64_t K, uint64_t i) {
-    double E = o_exp1(o_word(K, i, O_SLOT_VALUE));
+    double E = o_exp1(o_word(K, i, O_SLOT_POINT));
     if (P->variant == 2) E = P->beta[i] * E;
     return (uint64_t)(E * 0x1p32);
 }
@@ -287,7 +292,7 @@ static inline double o_value4(const o_params *P, uint64_t K, uint64_t i, double 
     if (i < m)
         return winv * (P->gam[i - 1] +
                        P->dgam[i] * o_te(K, i, P->lam4[i], P->c14[i], P->c24[i], P->c34[i]));
-    return winv * (P->gam[m - 1] + P->delta * o_exp1(o_word(K, i, O_SLOT_VALUE)));
+    return winv * (P->gam[m - 1] + P->delta * o_exp1(o_word(K, i, O_SLOT_POINT)));
 }
 
 /* Lazy Fisher-Yates permutation generator of Sec. 2.4 (arrays g, v and the

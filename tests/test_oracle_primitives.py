@@ -100,6 +100,7 @@ def test_word_stream_avalanche(oracle):
 
 
 def test_exp1_distribution(oracle):
+    """Exp(1) from the high 32 bits of a word by inversion."""
     rng = np.random.default_rng(5)
     K = int(rng.integers(0, 2**63))
     xs = np.array([oracle.exp1_of_word(oracle.word(K, i, 0)) for i in range(1, 40001)])
@@ -162,7 +163,7 @@ def test_truncated_exponential_fast_path_rate(oracle):
         K = 777 + m
         N = 40000
         hits = sum(1 for i in range(1, N + 1)
-                   if c1 * (float(oracle.word(K, i, 0) >> 11) * 2.0 ** -53) < 1.0)
+                   if c1 * (float(oracle.word(K, i, 0) >> 32) * 2.0 ** -32) < 1.0)
         sd = math.sqrt(expect * (1 - expect) / N)
         tol = max(4 * sd, gold["te_fast_path_worst"]["tolerance"] if lam_idx else 0)
         assert abs(hits / N - expect) < tol + 4 * sd
@@ -241,3 +242,16 @@ def test_stream_monotone_lower_bounds(oracle):
                 assert (xs >= winv * g).all()
             if v in (2, 4):
                 assert sorted(ls.tolist()) == list(range(m))
+
+
+def test_value_and_label_of_one_word_are_independent(oracle):
+    """The value uniform (high half) and the label (low half) of a point come
+    from one word; they must be independent: chi-square on the joint table of
+    value decile x label for m = 10."""
+    counts = np.zeros((10, 10))
+    K = oracle.mix64(99)
+    for i in range(1, 50001):
+        u = (oracle.word(K, i, 0) >> 32) / 2.0 ** 32
+        counts[int(u * 10), oracle.lemire(K, i, 10)] += 1
+    chi2, pval, _, _ = stats.chi2_contingency(counts)
+    assert pval > 1e-3
