@@ -141,8 +141,59 @@ double or_expm1(double t) {
     return p * t;
 }
 
+/* Table-driven logarithm for the streams' Exp(1) variates (the counterpart of
+ * the table-based exponential sampler of Sec. 3).  x = 2^e y, y = 1.m in
+ * [1,2); j = top 7 bits of m; cell centre c_j = 1 + (j + 1/2)/128, except
+ * c_0 = 1.  If y >= sqrt(2) the reduction uses y/2 against c_j/2 (c_127 = 2,
+ * so the cell below 1 is centred on 1) and exponent e+1.  With r =
+ * fma(y, 1/c_j, -1) (the same ratio in both cases), |r| <= 2^-7:
+ *   log x = e' ln2_hi + (e' ln2_lo + (L + log1p8(r))),  L = log(c'),
+ * log1p8(r) = r + r^2 (-1/2 + r/3 - ... + r^6/8) by Horner with fma.  The
+ * table (1/c_j, log c_j, log(c_j/2)) is built with the series logarithm. */
+static double o_ltab_inv[128], o_ltab_l[128], o_ltab_lh[128];
+static pthread_once_t o_ltab_once = PTHREAD_ONCE_INIT;
+static void o_ltab_init(void) {
+    for (int j = 0; j < 128; ++j) {
+        double c = (j == 0) ? 1.0 : 1.0 + ((double)j + 0.5) / 128.0;
+        if (j == 127) c = 2.0;
+        o_ltab_inv[j] = 1.0 / c;
+        /* log c' taken as -log of the stored reciprocal, so that
+         * log y = log(y inv) - log(inv) holds for the rounded inv itself */
+        o_ltab_l[j] = 0.0 - or_log(o_ltab_inv[j]);
+        o_ltab_lh[j] = 0.0 - or_log(2.0 * o_ltab_inv[j]);
+    }
+}
+
+double or_log_stream(double x) {
+    pthread_once(&o_ltab_once, o_ltab_init);
+    uint64_t b;
+    memcpy(&b, &x, 8);
+    int e = (int)((b >> 52) & 0x7FF) - 1023;
+    uint64_t mant = b & 0xFFFFFFFFFFFFFULL;
+    unsigned j = (unsigned)(mant >> 45);
+    uint64_t yb = mant | (1023ULL << 52);
+    double y;
+    memcpy(&y, &yb, 8);
+    double L = o_ltab_l[j];
+    if (mant >= 0x6A09E667F3BCDULL) { /* y >= sqrt(2) */
+        e += 1;
+        L = o_ltab_lh[j];
+    }
+    double r = fma(y, o_ltab_inv[j], -1.0);
+    double q = 1.0 / 8.0;
+    q = fma(q, r, -1.0 / 7.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, -1.0 / 5.0);
+    q = fma(q, r, 1.0 / 4.0);
+    q = fma(q, r, -1.0 / 3.0);
+    q = fma(q, r, 1.0 / 2.0);
+    double l1p = fma(-(r * r), q, r);
+    double de = (double)e;
+    return de * O_LN2_HI + (de * O_LN2_LO + (L + l1p));
+}
+
 /* Exp(1) by inversion; 0 - log(u) keeps the result +0 for u = 1. */
-static inline double o_exp1(uint64_t w) { return 0.0 - or_log(o_upos(w)); }
+static inline double o_exp1(uint64_t w) { return 0.0 - or_log_stream(o_upos(w)); }
 
 /* Uniform integer in [0, s), Lemire's multiply-and-reject method on the low
  * 32 bits of the point's word, redrawing from words 1..8 (at most 8 redraws). */

@@ -40,6 +40,29 @@ def test_log_accuracy_against_libm(oracle):
         assert abs(oracle.spec_log(x) - ref) <= 2 * ulp(ref)
 
 
+def test_stream_log_accuracy_against_libm(oracle):
+    """The table-driven logarithm of the streams (every 32-bit uniform grid
+    point class, plus general arguments) within 2 ulp of the C library."""
+    rng = np.random.default_rng(11)
+    ks = np.concatenate([rng.integers(1, 2**32 + 1, size=40000), np.arange(1, 300), 2**32 - np.arange(0, 300)])
+    for k in ks:
+        x = float(k) * 2.0 ** -32
+        ref = math.log(x)
+        got = oracle.stream_log(x)
+        if ref == 0.0:
+            assert got == 0.0
+        else:
+            assert abs(got - ref) <= 2 * ulp(ref), (x, got, ref)
+    # every table cell, both sides of the sqrt(2) split
+    for j in range(128):
+        for frac in (0.0, 0.25, 0.5, 0.999):
+            y = 1.0 + (j + frac) / 128.0
+            for e in (-40, -1, 0, 3):
+                x = math.ldexp(y, e)
+                ref = math.log(x)
+                assert abs(oracle.stream_log(x) - ref) <= 2 * ulp(ref), (j, frac, e)
+
+
 def test_log_exact_points(oracle):
     assert oracle.spec_log(1.0) == 0.0
     for k in range(-60, 61):
