@@ -151,14 +151,15 @@ int pmh_allpairs_counts(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* co
 /* Copy a constant table to [host] out (count doubles).  which: 0 beta (PMH2,
  * m+1), 1 lambda_i, 2 c1_i, 3 c2_i, 4 c3_i, 5 gamma_i, 6 dgamma_i (PMH4, m
  * each), 7 scalars {lambda, c1, c2, c3, delta, 0, 0, 0} (8), 8 expm1
- * coefficients (19).  Synchronous. */
+ * coefficients (19), 9 stream-logarithm cells (512: 256 pairs (1/c_j, L_j)).
+ * Synchronous. */
 int pmh_get_table(pmh_ctx* ctx, int which, double* out, uint32_t count);
 
 /* Evaluate one primitive of the random streams elementwise on [device]
  * arrays (for validation): what 0 log(in), 1 log1p(in), 2 expm1(in),
  * 3 Exp(1) from word in_u, 4 mix64(in_u), 5 truncated exponential of element
  * key in_u[k] at point k+1 (PMH3 constants), 6 Lemire(m) label of that point,
- * 7 ProbMinHash1 fixed-point spacing of that point. */
+ * 7 ProbMinHash1 fixed-point spacing of that point, 8 stream logarithm(in). */
 int pmh_debug_eval(pmh_ctx* ctx, int what, const double* in, const uint64_t* in_u, double* out,
                    uint64_t* out_u, uint64_t n, void* stream);
 

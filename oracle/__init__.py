@@ -61,7 +61,7 @@ def lib():
         vp = ctypes.c_void_p
         sig = {
             "or_log": (dbl, [dbl]), "or_log1p": (dbl, [dbl]), "or_expm1": (dbl, [dbl]),
-            "or_log_stream": (dbl, [dbl]),
+            "or_log_stream": (dbl, [dbl]), "or_log_table": (None, [vp]),
             "or_seedhash": (u64, [u64]), "or_mix64": (u64, [u64]),
             "or_word": (u64, [u64, u64, ctypes.c_uint]), "or_exp1_word": (dbl, [u64]),
             "or_lemire": (u32, [u64, u64, u32]), "or_te": (dbl, [u64, u64, dbl, dbl, dbl, dbl]),
@@ -100,6 +100,12 @@ def spec_log(x: float) -> float:
 def stream_log(x: float) -> float:
     """Table-driven logarithm behind the streams' Exp(1) variates."""
     return lib().or_log_stream(float(x))
+
+
+def stream_log_table() -> np.ndarray:
+    out = np.zeros(512, dtype=np.float64)
+    lib().or_log_table(_ptr(out))
+    return out
 
 
 def spec_log1p(x: float) -> float:

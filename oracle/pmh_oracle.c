@@ -192,6 +192,17 @@ double or_log_stream(double x) {
     return de * O_LN2_HI + (de * O_LN2_LO + (L + l1p));
 }
 
+/* The 256 (1/c, L) cells in the layout [j + 128 h] (for the tests). */
+void or_log_table(double* out512) {
+    pthread_once(&o_ltab_once, o_ltab_init);
+    for (int j = 0; j < 128; ++j) {
+        out512[2 * j] = o_ltab_inv[j];
+        out512[2 * j + 1] = o_ltab_l[j];
+        out512[2 * (128 + j)] = o_ltab_inv[j];
+        out512[2 * (128 + j) + 1] = o_ltab_lh[j];
+    }
+}
+
 /* Exp(1) by inversion; 0 - log(u) keeps the result +0 for u = 1. */
 static inline double o_exp1(uint64_t w) { return 0.0 - or_log_stream(o_upos(w)); }
 

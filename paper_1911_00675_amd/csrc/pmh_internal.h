@@ -28,6 +28,7 @@ struct Tables {
   double* dgam;   // PMH4: [m], gamma_i - gamma_{i-1}
   double* expm1c; // [19] Taylor coefficients 1/k! built by repeated division
   double* scal;   // [8]: lambda, c1, c2, c3 (PMH3), delta (PMH4)
+  double* ltab;   // [512]: stream-logarithm cells (inv_j, -log inv_j), then (inv_j, -log 2 inv_j)
 };
 
 // Tunables of the per-set algorithm (chosen by the autotuner or defaults).

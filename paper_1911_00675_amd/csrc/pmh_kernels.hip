@@ -41,6 +41,16 @@ constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
 constexpr uint32_t kFyLaneSteps = 4;             // lane-mode Fisher-Yates steps kept in registers
 constexpr uint32_t kEpt = 2;                     // elements per thread per batch
 
+// Optional event counters (statistics build only, -DPMH_STATS): accumulated in
+// LDS per workgroup and added to HashArgs::points[0..15] when a set ends.
+#ifdef PMH_STATS
+#define PMH_STAT(sm, i, v) atomicAdd(&(sm).st[i], (uint32_t)(v))
+#else
+#define PMH_STAT(sm, i, v) ((void)0)
+#endif
+enum { kStSets, kStRounds, kStElems, kStLanePts, kStLaneIters, kStLaneApply, kStMiniSteps, kStMiniPts,
+       kStMiniElems, kStChainTiles, kStChainPts, kStChainElems, kStFlush, kStBlockMax, kStApply, kStCount };
+
 // ---------------------------------------------------------------- randomness
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -48,13 +58,17 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 // Word slot t of point i of element K is mix64(K + ((i << 8) + t + 1) * phi);
-// pbase folds the point-independent part so slot t costs one add.
+// pbase folds the point-independent part so slot t costs one add, and point
+// i+1's base is point i's plus kPointStep.  Word 0 of a point serves twice:
+// high 32 bits -> the uniform behind the value, low 32 bits -> the label draw.
+constexpr uint64_t kPointStep = 256ull * kPhi;
 __device__ __forceinline__ uint64_t pbase(uint64_t K, uint32_t i) {
   return K + (uint64_t)((i << 8) + 1u) * kPhi;
 }
 __device__ __forceinline__ uint64_t word(uint64_t pb, uint32_t t) { return mix64(pb + (uint64_t)t * kPhi); }
+__device__ __forceinline__ double u32v(uint64_t w) { return (double)(uint32_t)(w >> 32) * 0x1p-32; }
+__device__ __forceinline__ double upos32(uint64_t w) { return (double)((w >> 32) + 1) * 0x1p-32; }
 __device__ __forceinline__ double u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
-__device__ __forceinline__ double upos(uint64_t w) { return (double)((w >> 11) + 1) * 0x1p-53; }
 
 // ln x = e ln 2 + 2 atanh(s), x = 2^e f, f in [sqrt(1/2), sqrt(2)), s = (f-1)/(f+1).
 __device__ __forceinline__ double spec_log(double x) {
@@ -97,7 +111,35 @@ __device__ __forceinline__ double spec_expm1(double t, const double* c) {
   return p * t;
 }
 
-__device__ __forceinline__ double exp1(uint64_t w) { return 0.0 - spec_log(upos(w)); }
+// Table-driven logarithm of the streams: x = 2^e y, cell j = top 7 mantissa
+// bits, r = fma(y, inv_j, -1), log1p by a degree-8 polynomial;
+// tab[j + 128 h] = (inv_j, -log(inv_j)) with h = 0, or (inv_j, -log(2 inv_j))
+// with h = 1 when y >= sqrt(2) (exponent e+1).
+struct LogCell {
+  double inv, L;
+};
+__device__ __forceinline__ double stream_log(double x, const LogCell* tab) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  int e = (int)((b >> 52) & 0x7FF) - 1023;
+  const uint64_t mant = b & 0xFFFFFFFFFFFFFull;
+  const uint32_t j = (uint32_t)(mant >> 45);
+  const bool halve = mant >= 0x6A09E667F3BCDull;
+  e += halve ? 1 : 0;
+  const LogCell c = tab[j + (halve ? 128u : 0u)];
+  const double y = __longlong_as_double((long long)(mant | (1023ull << 52)));
+  const double r = __builtin_fma(y, c.inv, -1.0);
+  double q = 1.0 / 8.0;
+  q = __builtin_fma(q, r, -1.0 / 7.0);
+  q = __builtin_fma(q, r, 1.0 / 6.0);
+  q = __builtin_fma(q, r, -1.0 / 5.0);
+  q = __builtin_fma(q, r, 1.0 / 4.0);
+  q = __builtin_fma(q, r, -1.0 / 3.0);
+  q = __builtin_fma(q, r, 1.0 / 2.0);
+  const double l1p = __builtin_fma(-(r * r), q, r);
+  const double de = (double)e;
+  return de * kLn2Hi + (de * kLn2Lo + (c.L + l1p));
+}
+__device__ __forceinline__ double exp1(uint64_t w, const LogCell* tab) { return 0.0 - stream_log(upos32(w), tab); }
 
 // Rejection part of the truncated-exponential sampler (Sec. 2.8).
 __device__ __attribute__((noinline)) double te_slow(uint64_t pb, double lam, double c1, double c2,
@@ -119,10 +161,10 @@ __device__ __attribute__((noinline)) double te_slow(uint64_t pb, double lam, dou
   return x;
 }
 // Exp(lam; 0, 1): the rectangle below e^-lam first (taken with probability
-// lam/(e^lam - 1)), rejection otherwise.
-__device__ __forceinline__ double trunc_exp(uint64_t pb, double lam, double c1, double c2, double c3,
+// lam/(e^lam - 1)), rejection otherwise.  w0 = the point's word 0.
+__device__ __forceinline__ double trunc_exp(uint64_t w0, uint64_t pb, double lam, double c1, double c2, double c3,
                                             const double* em) {
-  double x = c1 * u53(mix64(pb));
+  double x = c1 * u32v(w0);
   if (x < 1.0) return x;
   return te_slow(pb, lam, c1, c2, c3, em);
 }
@@ -131,15 +173,16 @@ __device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_
   uint32_t thr = (0u - s) % s;
   uint32_t lo = (uint32_t)prod;
   for (uint32_t r = 1; lo < thr && r <= 8; ++r) {
-    uint64_t x = word(pb, 1u + r) >> 32;
+    uint64_t x = word(pb, r) & 0xFFFFFFFFull;
     prod = x * (uint64_t)s;
     lo = (uint32_t)prod;
   }
   return prod;
 }
-// Uniform integer in [0, s) (Lemire's multiply-shift with rejection).
-__device__ __forceinline__ uint32_t lemire(uint64_t pb, uint32_t s) {
-  uint64_t x = word(pb, 1u) >> 32;
+// Uniform integer in [0, s) (Lemire's multiply-shift with rejection) from the
+// low half of the point's word 0; redraws from words 1..8.
+__device__ __forceinline__ uint32_t lemire(uint64_t w0, uint64_t pb, uint32_t s) {
+  uint64_t x = w0 & 0xFFFFFFFFull;
   uint64_t prod = x * (uint64_t)s;
   if ((uint32_t)prod < s) prod = lemire_redraw(pb, s, prod);
   return (uint32_t)(prod >> 32);
@@ -205,6 +248,9 @@ struct Shared {
   uint32_t qhead, qtail;  // long-chain queue: front of the queue array
   uint32_t mhead, mtail;  // mini-chain queue: back of the queue array
   uint32_t item;
+#ifdef PMH_STATS
+  uint32_t st[16];
+#endif
 };
 
 // Per-round view of one set, kept in registers.
@@ -215,6 +261,7 @@ struct Round {
   uint32_t qcap;
   uint64_t K0;     // seed hash
   double T, Tprev; // generate points below T; points below Tprev were handled
+  const LogCell* lt;  // logarithm table (LDS copy)
 };
 
 __device__ __forceinline__ uint64_t shared_kmax(Shared& sm) {
@@ -233,6 +280,7 @@ __device__ uint64_t block_max_keys(const uint64_t* keys, uint32_t m, Shared& sm)
   if (lane == 0) sm.red_u[wv] = v;
   __syncthreads();
   if (tid == 0) {
+    PMH_STAT(sm, kStBlockMax, 1);
     uint64_t r = sm.red_u[0];
     for (int i = 1; i < NW; ++i) r = sm.red_u[i] > r ? sm.red_u[i] : r;
     sm.kmax = r;
@@ -265,45 +313,56 @@ __device__ __forceinline__ void push_mini(Shared& sm, ChainEntry* q, uint32_t qc
 // Returns after the element's points below R.T are applied, or after pushing
 // the element to a chain queue.
 template <int V>
-__device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uint32_t p, double winv,
+__device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint32_t p, double winv,
                                           uint64_t K, uint64_t kmax, uint64_t* keys, Shared& sm,
                                           ChainEntry* q, int budget) {
   const Tables& t = A.t;
   const uint32_t m = R.m;
+  const LogCell* lt = R.lt;
   if constexpr (V == 1) {
     uint64_t tacc = 0;
     uint32_t i = 1;
-    for (int step = 0;; ++step) {
+    uint64_t pb = pbase(K, 1);
+    for (int step = 0;; ++step, pb += kPointStep) {
       if (step == budget) {
         push_mini(sm, q, R.qcap, p, i, tacc);
-        return;
+        return step;
       }
-      const uint64_t pb = pbase(K, i);
-      tacc += (uint64_t)(exp1(mix64(pb)) * 0x1p32);
+      const uint64_t w0 = mix64(pb);
+      tacc += (uint64_t)(exp1(w0, lt) * 0x1p32);
       const double x = winv * ((double)tacc * 0x1p-32);
-      if (!(x < R.T)) return;
+      PMH_STAT(sm, kStLanePts, 1);
+      if (!(x < R.T)) return step + 1;
       const uint64_t key = make_key(x, p);
-      if (key >= kmax) return;
-      if (x >= R.Tprev) lds_min(keys, lemire(pb, m), key);
-      if (i == R.imax) return;
+      if (key >= kmax) return step + 1;
+      if (x >= R.Tprev) {
+        PMH_STAT(sm, kStLaneApply, 1);
+        lds_min(keys, lemire(w0, pb, m), key);
+      }
+      if (i == R.imax) return step + 1;
       ++i;
     }
   } else if constexpr (V == 3) {
     const double lam = t.scal[0], c1 = t.scal[1], c2 = t.scal[2], c3 = t.scal[3];
     uint32_t i = 1;
-    for (int step = 0;; ++step) {
+    uint64_t pb = pbase(K, 1);
+    for (int step = 0;; ++step, pb += kPointStep) {
       const double lb = winv * (double)(i - 1);
-      if (!(lb < R.T)) return;
-      if (make_key(lb, p) >= kmax) return;
+      if (!(lb < R.T)) return step;
+      if (make_key(lb, p) >= kmax) return step;
       if (step == budget) {
         push_mini(sm, q, R.qcap, p, i, 0);
-        return;
+        return step;
       }
-      const uint64_t pb = pbase(K, i);
-      const double x = lb + winv * trunc_exp(pb, lam, c1, c2, c3, t.expm1c);
+      const uint64_t w0 = mix64(pb);
+      const double x = lb + winv * trunc_exp(w0, pb, lam, c1, c2, c3, t.expm1c);
       const uint64_t key = make_key(x, p);
-      if (x >= R.Tprev && key < kmax) lds_min(keys, lemire(pb, m), key);
-      if (i == R.imax) return;
+      PMH_STAT(sm, kStLanePts, 1);
+      if (x >= R.Tprev && key < kmax) {
+        PMH_STAT(sm, kStLaneApply, 1);
+        lds_min(keys, lemire(w0, pb, m), key);
+      }
+      if (i == R.imax) return step + 1;
       ++i;
     }
   } else {
@@ -314,25 +373,26 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
 #pragma unroll
     for (uint32_t step = 0; step < kFyLaneSteps; ++step) {
       const uint32_t i = step + 1;
-      if (i > m) return;
+      if (i > m) return (int)step;
       const uint64_t pb = pbase(K, i);
+      const uint64_t w0 = mix64(pb);
       double x;
       if constexpr (V == 2) {
-        tacc += (uint64_t)((t.beta[i] * exp1(mix64(pb))) * 0x1p32);
+        tacc += (uint64_t)((t.beta[i] * exp1(w0, lt)) * 0x1p32);
         x = winv * ((double)tacc * 0x1p-32);
-        if (!(x < R.T)) return;
-        if (make_key(x, p) >= kmax) return;
+        if (!(x < R.T)) return (int)step + 1;
+        if (make_key(x, p) >= kmax) return (int)step + 1;
       } else {
         const double lb = winv * t.gam[i - 1];
-        if (!(lb < R.T)) return;
-        if (make_key(lb, p) >= kmax) return;
+        if (!(lb < R.T)) return (int)step;
+        if (make_key(lb, p) >= kmax) return (int)step;
         if (i < m)
-          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
+          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
         else
-          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(mix64(pb)));
+          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(w0, lt));
       }
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
-      const uint32_t j = (i - 1) + lemire(pb, m - i + 1);
+      const uint32_t j = (i - 1) + lemire(w0, pb, m - i + 1);
       uint32_t l = j, v = i - 1;
 #pragma unroll
       for (uint32_t s = 0; s < step; ++s) {
@@ -343,9 +403,10 @@ __device__ __forceinline__ void lane_elem(const HashArgs& A, const Round& R, uin
       vv[step] = v;
       const uint64_t key = make_key(x, p);
       if (x >= R.Tprev && key < kmax) lds_min(keys, l, key);
-      if (i == m) return;
+      if (i == m) return (int)step + 1;
     }
     push_long(sm, q, p, 1, 0);
+    return (int)kFyLaneSteps;
   }
 }
 
@@ -357,6 +418,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
   const Tables& t = A.t;
   const int lane = threadIdx.x & 63;
   const uint32_t m = R.m;
+  const LogCell* lt = R.lt;
   const uint32_t p = e.p;
   const double winv = 1.0 / R.w[p];
   const uint64_t K = mix64(R.ids[p] ^ R.K0);
@@ -364,16 +426,18 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
   uint64_t kmax = shared_kmax(sm);
   uint32_t i0 = e.i;
   uint64_t tacc = e.tacc;
+  if (lane == 0) PMH_STAT(sm, kStChainElems, 1);
   if constexpr (V == 2 || V == 4) {
     i0 = 1;
     tacc = 0;
     for (uint32_t k = lane; k < m; k += 64) g[k] = (uint16_t)k;
     __builtin_amdgcn_wave_barrier();
   }
-  for (uint32_t tile = 1;; ++tile) {
+  uint64_t pb = pbase(K, i0) + (uint64_t)lane * kPointStep;
+  for (uint32_t tile = 1;; ++tile, pb += 64ull * kPointStep) {
     const uint32_t i = i0 + (uint32_t)lane;
     const bool valid = i <= end;
-    const uint64_t pb = pbase(K, i);
+    const uint64_t w0 = mix64(pb);
     double x = 0.0;
     uint64_t key = kEmptyKey;
     bool stop;
@@ -381,7 +445,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
     if constexpr (V == 1 || V == 2) {
       uint64_t d = 0;
       if (valid) {
-        double E = exp1(mix64(pb));
+        double E = exp1(w0, lt);
         if constexpr (V == 2) E = t.beta[i] * E;
         d = (uint64_t)(E * 0x1p32);
       }
@@ -393,7 +457,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = lb + winv * trunc_exp(pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        x = lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
         key = make_key(x, p);
       }
     } else {
@@ -404,9 +468,9 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
       }
       if (!stop) {
         if (i < m)
-          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
+          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
         else
-          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(mix64(pb)));
+          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(w0, lt));
         key = make_key(x, p);
       }
     }
@@ -414,16 +478,20 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
     const int first = stopmask ? __builtin_ctzll(stopmask) : 64;
     const bool active = lane < first;
     const bool apply = active && x >= R.Tprev && key < kmax;
+    if (lane == 0) {
+      PMH_STAT(sm, kStChainTiles, 1);
+      PMH_STAT(sm, kStChainPts, first);
+    }
     uint32_t label = 0;
     if constexpr (V == 1 || V == 3) {
-      if (apply) label = lemire(pb, m);
+      if (apply) label = lemire(w0, pb, m);
     } else {
       // 64 Fisher-Yates steps at once.  Step L (point i0+L) consumes position
       // P = i-1 and draws slot j >= P; its label is g[j] and it writes the old
       // g[P] into slot j.  Dependencies inside the tile are resolved by finding,
       // for each step, the latest earlier step that wrote its slot or position.
       const int P = (int)i - 1;
-      const int j = active ? P + (int)lemire(pb, m - i + 1) : -1;
+      const int j = active ? P + (int)lemire(w0, pb, m - i + 1) : -1;
       int lastJ = -1, lastP = -1;
       bool later = false;
       for (int s = 0; s < 64; ++s) {
@@ -454,7 +522,10 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint
       if (first == 64 && active && !later) g[j] = (uint16_t)v;
       __builtin_amdgcn_wave_barrier();
     }
-    if (apply) lds_min(keys, label, key);
+    if (apply) {
+      PMH_STAT(sm, kStApply, 1);
+      lds_min(keys, label, key);
+    }
     if (first < 64) break;
     if constexpr (V == 1 || V == 2) tacc = shfl_u64(tl, 63);
     i0 += 64;
@@ -476,10 +547,11 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
   const int lane = threadIdx.x & 63;
   const int j = lane & 7, leader = lane & ~7, grp = lane >> 3;
   const uint32_t m = R.m, end = R.imax;
+  const LogCell* lt = R.lt;
   const uint32_t mtail = sm.mtail;
   bool have = false;
   uint32_t p = 0, i0 = 1;
-  uint64_t tacc = 0, K = 0;
+  uint64_t tacc = 0, K = 0, pb = 0;
   double winv = 0.0;
   uint64_t kmax = shared_kmax(sm);
   for (uint32_t step = 0;; ++step) {
@@ -494,18 +566,20 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
         tacc = ce.tacc;
         winv = 1.0 / R.w[p];
         K = mix64(R.ids[p] ^ R.K0);
+        pb = pbase(K, i0) + (uint64_t)j * kPointStep;
         have = true;
+        if (j == 0) PMH_STAT(sm, kStMiniElems, 1);
       }
     }
     if (__ballot(have) == 0) break;
     const uint32_t i = i0 + (uint32_t)j;
     const bool valid = have && i <= end;
-    const uint64_t pb = pbase(K, i);
+    const uint64_t w0 = mix64(pb);
     double x = 0.0;
     uint64_t key = kEmptyKey, tl = 0;
     bool stop;
     if constexpr (V == 1) {
-      uint64_t d = valid ? (uint64_t)(exp1(mix64(pb)) * 0x1p32) : 0;
+      uint64_t d = valid ? (uint64_t)(exp1(w0, lt) * 0x1p32) : 0;
       for (int dd = 1; dd < 8; dd <<= 1) {
         const uint64_t o = shfl_u64(d, lane - dd >= leader ? lane - dd : lane);
         if (j >= dd) d += o;
@@ -518,7 +592,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = lb + winv * trunc_exp(pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        x = lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
         key = make_key(x, p);
       }
     }
@@ -526,13 +600,19 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
     const uint32_t bits = (uint32_t)(smask >> (grp * 8)) & 0xFFu;
     const int first = __builtin_ctz(bits | 0x100u);
     const bool apply = have && j < first && x >= R.Tprev && key < kmax;
-    if (apply) lds_min(keys, lemire(pb, m), key);
+    if (lane == 0) PMH_STAT(sm, kStMiniSteps, 1);
+    if (have && j == 0) PMH_STAT(sm, kStMiniPts, first);
+    if (apply) {
+      PMH_STAT(sm, kStApply, 1);
+      lds_min(keys, lemire(w0, pb, m), key);
+    }
     const uint64_t tlast = shfl_u64(tl, leader + 7);
     if (have) {
       if (first < 8) {
         have = false;
       } else {
         i0 += 8;
+        pb += 8ull * kPointStep;
         tacc = tlast;
       }
     }
@@ -568,7 +648,7 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
 // ------------------------------------------------------------- one set
 template <int V, int NW>
 __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
-                            uint16_t* fy, Shared& sm) {
+                            uint16_t* fy, const LogCell* lt, Shared& sm) {
   constexpr int BS = NW * 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t m = A.m;
@@ -582,8 +662,14 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
   R.imax = A.imax;
   R.qcap = qcap;
   R.K0 = A.seedhash;
+  R.lt = lt;
   if (n64 > kMaxSet && tid == 0) atomicOr(A.status, kStatusSetTooLarge);
 
+#ifdef PMH_STATS
+  if (tid < 16) sm.st[tid] = 0;
+  __syncthreads();
+  if (tid == 0) PMH_STAT(sm, kStSets, 1);
+#endif
   for (uint32_t k = tid; k < m; k += BS) keys[k] = kEmptyKey;
   // total weight (first threshold) and weight validation
   double ws = 0.0;
@@ -612,6 +698,7 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
         sm.kmax = kmax_round;
         sm.qhead = sm.qtail = 0;
         sm.mhead = sm.mtail = 0;
+        PMH_STAT(sm, kStRounds, 1);
       }
       __syncthreads();
       const uint32_t batch = kEpt * BS;
@@ -623,6 +710,7 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
           if (p >= R.n) break;
           const double w = R.w[p];
           if (!weight_ok(w)) continue;
+          PMH_STAT(sm, kStElems, 1);
           const double lam = w * R.T;  // expected points below T
           if (lam > A.chain_expect) {
             push_long(sm, q, p, 1, 0);
@@ -634,12 +722,21 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
           }
           const double winv = 1.0 / w;
           const uint64_t K = mix64(R.ids[p] ^ R.K0);
-          lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
+          const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
+#ifdef PMH_STATS
+          // wave-level cost of this element slot: the longest lane
+          int mx = steps;
+          for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+          if (lane == __builtin_ctzll(__ballot(true))) PMH_STAT(sm, kStLaneIters, mx);
+#else
+          (void)steps;
+#endif
         }
         __syncthreads();
         const uint32_t qt = sm.qtail + sm.mtail;  // read by every thread before anyone pushes again
         __syncthreads();
         const bool flush = qt + batch > qcap;
+        if (flush && tid == 0) PMH_STAT(sm, kStFlush, 1);
         if (flush) chain_pass<V, NW>(A, R, keys, q, fy, sm);
         if (flush || (nb % (uint32_t)A.kmax_refresh) == (uint32_t)A.kmax_refresh - 1) block_max_keys<NW>(keys, m, sm);
       }
@@ -666,46 +763,59 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
     if (A.out_id) A.out_id[o + k] = empty ? 0ull : R.ids[pos];
   }
   __syncthreads();
+#ifdef PMH_STATS
+  if (tid < kStCount && A.points) atomicAdd((unsigned long long*)&A.points[tid], (unsigned long long)sm.st[tid]);
+#endif
 }
 
+// Dynamic LDS: log table (256 cells) | keys[m] | chain queue | Fisher-Yates arrays.
+constexpr uint32_t kLogCells = 256;
 template <int V, int NW>
-__device__ __forceinline__ void carve(uint64_t*& keys, ChainEntry*& q, uint32_t& qcap, uint16_t*& fy,
-                                      uint32_t m) {
+__device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*& keys, ChainEntry*& q,
+                                      uint32_t& qcap, uint16_t*& fy) {
   extern __shared__ __align__(16) unsigned char dyn[];
-  keys = reinterpret_cast<uint64_t*>(dyn);
-  q = reinterpret_cast<ChainEntry*>(dyn + (size_t)m * 8);
+  const uint32_t m = A.m;
+  lt = reinterpret_cast<LogCell*>(dyn);
+  unsigned char* base = dyn + kLogCells * sizeof(LogCell);
+  keys = reinterpret_cast<uint64_t*>(base);
+  q = reinterpret_cast<ChainEntry*>(base + (size_t)m * 8);
   qcap = 2 * kEpt * NW * 64;
-  fy = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(dyn + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry))
+  fy = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(base + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry))
                           : nullptr;
+  const LogCell* src = reinterpret_cast<const LogCell*>(A.t.ltab);
+  for (uint32_t k = threadIdx.x; k < kLogCells; k += NW * 64) lt[k] = src[k];
+  __syncthreads();
 }
 
 template <int V, int NW>
 __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
   __shared__ Shared sm;
+  LogCell* lt;
   uint64_t* keys;
   ChainEntry* q;
   uint32_t qcap;
   uint16_t* fy;
-  carve<V, NW>(keys, q, qcap, fy, A.m);
+  carve<V, NW>(A, lt, keys, q, qcap, fy);
   for (;;) {
     if (threadIdx.x == 0) sm.item = atomicAdd(A.counter, 1u);
     __syncthreads();
     const uint32_t item = sm.item;
     __syncthreads();
     if (item >= A.num_items) break;
-    process_set<V, NW>(A, A.order ? A.order[item] : item, keys, q, qcap, fy, sm);
+    process_set<V, NW>(A, A.order ? A.order[item] : item, keys, q, qcap, fy, lt, sm);
   }
 }
 
 template <int V, int NW>
 __global__ __launch_bounds__(NW * 64) void k_hash_one(HashArgs A, uint64_t set) {
   __shared__ Shared sm;
+  LogCell* lt;
   uint64_t* keys;
   ChainEntry* q;
   uint32_t qcap;
   uint16_t* fy;
-  carve<V, NW>(keys, q, qcap, fy, A.m);
-  process_set<V, NW>(A, set, keys, q, qcap, fy, sm);
+  carve<V, NW>(A, lt, keys, q, qcap, fy);
+  process_set<V, NW>(A, set, keys, q, qcap, fy, lt, sm);
 }
 
 // ------------------------------------------------------ heavy-first order
@@ -747,6 +857,14 @@ __global__ void k_init_tables(int variant, uint32_t m, Tables t) {
   if (i == 0) {
     t.expm1c[0] = 1.0;
     for (int k = 1; k <= 18; ++k) t.expm1c[k] = t.expm1c[k - 1] / (double)k;
+  }
+  if (i < 128) {  // stream logarithm cells: centre 1 + (j + 1/2)/128, c_0 = 1, c_127 = 2
+    const double c = i == 0 ? 1.0 : (i == 127 ? 2.0 : 1.0 + ((double)i + 0.5) / 128.0);
+    const double inv = 1.0 / c;
+    t.ltab[2 * i] = inv;
+    t.ltab[2 * i + 1] = 0.0 - spec_log(inv);
+    t.ltab[2 * (128 + i)] = inv;
+    t.ltab[2 * (128 + i) + 1] = 0.0 - spec_log(2.0 * inv);
   }
   if (variant == 2 && i <= m) t.beta[i] = i == 0 ? 0.0 : (double)m / (double)(m - i + 1);
   if (variant == 3 && i == 0) {
@@ -852,11 +970,20 @@ __global__ void k_debug(int what, const double* in, const uint64_t* in_u, double
     case 0: out[k] = spec_log(in[k]); break;
     case 1: out[k] = spec_log1p(in[k]); break;
     case 2: out[k] = spec_expm1(in[k], t.expm1c); break;
-    case 3: out[k] = exp1(in_u[k]); break;
+    case 3: out[k] = exp1(in_u[k], (const LogCell*)t.ltab); break;
     case 4: out_u[k] = mix64(in_u[k]); break;
-    case 5: out[k] = trunc_exp(pbase(in_u[k], (uint32_t)k + 1), t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c); break;
-    case 6: out_u[k] = lemire(pbase(in_u[k], (uint32_t)k + 1), m); break;
-    case 7: out_u[k] = (uint64_t)(exp1(mix64(pbase(in_u[k], (uint32_t)k + 1))) * 0x1p32); break;
+    case 5: {
+      const uint64_t pb = pbase(in_u[k], (uint32_t)k + 1);
+      out[k] = trunc_exp(mix64(pb), pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+      break;
+    }
+    case 6: {
+      const uint64_t pb = pbase(in_u[k], (uint32_t)k + 1);
+      out_u[k] = lemire(mix64(pb), pb, m);
+      break;
+    }
+    case 7: out_u[k] = (uint64_t)(exp1(mix64(pbase(in_u[k], (uint32_t)k + 1)), (const LogCell*)t.ltab) * 0x1p32); break;
+    case 8: out[k] = stream_log(in[k], (const LogCell*)t.ltab); break;
     default: break;
   }
 }
@@ -866,7 +993,7 @@ __global__ void k_debug(int what, const double* in, const uint64_t* in_u, double
 // ------------------------------------------------------------------ launchers
 size_t lds_bytes(int variant, uint32_t m, int waves) {
   const size_t qcap = 2 * kEpt * (size_t)waves * 64;
-  size_t b = (size_t)m * 8 + qcap * sizeof(ChainEntry);
+  size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + qcap * sizeof(ChainEntry);
   if (variant == 2 || variant == 4) b += (size_t)waves * m * 2;
   return b;
 }
@@ -924,7 +1051,7 @@ hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t* order,
 }
 
 hipError_t launch_init_tables(int variant, uint32_t m, Tables t, hipStream_t s) {
-  const uint32_t n = m + 1;
+  const uint32_t n = (m + 1) > 128 ? (m + 1) : 128;
   hipLaunchKernelGGL(k_init_tables, dim3((n + 255) / 256), dim3(256), 0, s, variant, m, t);
   return hipGetLastError();
 }

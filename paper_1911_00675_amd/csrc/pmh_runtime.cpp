@@ -92,7 +92,7 @@ HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const
   a.order = wb ? wb->order : nullptr;
   a.counter = wb ? wb->counter : nullptr;
   a.num_items = (uint32_t)num_sets;
-  a.points = nullptr;
+  a.points = c->stats;
   return a;
 }
 
@@ -165,8 +165,8 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
     return PMH_ERR_DEVICE;
   }
   c->num_cu = prop.multiProcessorCount;
-  // constant tables: 7 arrays of m+1 doubles + expm1 (19) + scalars (8)
-  const size_t nd = 7 * (size_t)(m + 1) + 19 + 8;
+  // constant tables: 7 arrays of m+1 doubles + expm1 (19) + scalars (8) + log cells (512)
+  const size_t nd = 7 * (size_t)(m + 1) + 19 + 8 + 512;
   if (hipMalloc(&c->table_mem, nd * sizeof(double)) != hipSuccess) {
     delete c;
     return PMH_ERR_OOM;
@@ -181,10 +181,15 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   c->t.dgam = d + 6 * (size_t)(m + 1);
   c->t.expm1c = d + 7 * (size_t)(m + 1);
   c->t.scal = c->t.expm1c + 19;
+  c->t.ltab = c->t.scal + 8;
   int rc = PMH_OK;
   if (hipMemset(c->table_mem, 0, nd * sizeof(double)) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipMalloc(&c->status, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_OOM;
   if (!rc && hipMemset(c->status, 0, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
+#ifdef PMH_STATS
+  if (!rc && hipMalloc(&c->stats, 16 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_OOM;
+  if (!rc && hipMemset(c->stats, 0, 16 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
+#endif
   if (!rc && launch_init_tables(variant, m, c->t, nullptr) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) rc = PMH_ERR_DEVICE;
@@ -207,6 +212,7 @@ void pmh_destroy(pmh_ctx* c) {
   if (c->work.counter) (void)hipFree(c->work.counter);
   if (c->table_mem) (void)hipFree(c->table_mem);
   if (c->status) (void)hipFree(c->status);
+  if (c->stats) (void)hipFree(c->stats);
   delete c;
 }
 
@@ -367,6 +373,7 @@ int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
     case 6: src = c->t.dgam; avail = c->m; break;
     case 7: src = c->t.scal; avail = 8; break;
     case 8: src = c->t.expm1c; avail = 19; break;
+    case 9: src = c->t.ltab; avail = 512; break;
     default: return PMH_ERR_ARG;
   }
   if (count > avail) return PMH_ERR_ARG;
@@ -376,8 +383,8 @@ int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
 
 int pmh_debug_eval(pmh_ctx* c, int what, const double* in, const uint64_t* in_u, double* out, uint64_t* out_u,
                    uint64_t n, void* stream) {
-  if (!c || what < 0 || what > 7) return PMH_ERR_ARG;
-  const bool uses_u = what >= 3;
+  if (!c || what < 0 || what > 8) return PMH_ERR_ARG;
+  const bool uses_u = what >= 3 && what <= 7;
   const bool out_is_u = what == 4 || what == 6 || what == 7;
   if ((uses_u && !in_u) || (!uses_u && !in) || (out_is_u && !out_u) || (!out_is_u && !out)) return PMH_ERR_ARG;
   if (what == 5 && c->variant != 3) return PMH_ERR_ARG;
@@ -386,5 +393,18 @@ int pmh_debug_eval(pmh_ctx* c, int what, const double* in, const uint64_t* in_u,
              ? PMH_OK
              : PMH_ERR_DEVICE;
 }
+
+#ifdef PMH_STATS
+// Statistics build only (not part of the product ABI): read and optionally
+// reset the 16 event counters accumulated by the kernels.
+int pmh_stats_read(pmh_ctx* c, uint64_t* out16, int reset) {
+  if (!c || !out16 || !c->stats) return PMH_ERR_ARG;
+  DeviceGuard g(c->device);
+  if (hipDeviceSynchronize() != hipSuccess) return PMH_ERR_DEVICE;
+  if (hipMemcpy(out16, c->stats, 16 * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return PMH_ERR_DEVICE;
+  if (reset && hipMemset(c->stats, 0, 16 * sizeof(uint64_t)) != hipSuccess) return PMH_ERR_DEVICE;
+  return PMH_OK;
+}
+#endif
 
 }  // extern "C"

@@ -59,6 +59,7 @@ struct pmh_ctx {
   void* table_mem = nullptr;
   pmh::Tables t{};
   uint32_t* status = nullptr;
+  uint64_t* stats = nullptr;  // event counters of the statistics build
   pmh::WorkBuf work;
   pmh::Tuning tune;
   uint64_t tune_version = 0;

@@ -70,6 +70,10 @@ def test_primitives_bitwise(pmh):
     assert np.array_equal(te.view(np.uint64), want.view(np.uint64))
     lab = ctx.debug_eval(6, Ks)
     assert np.array_equal(lab, np.array([O.lemire(int(K), k + 1, m) for k, K in enumerate(Ks)], dtype=np.uint64))
+    xs = np.concatenate([u, np.exp(rng.uniform(-700, 700, 5000))])
+    assert np.array_equal(ctx.debug_eval(8, xs).view(np.uint64),
+                          np.array([O.stream_log(v) for v in xs]).view(np.uint64))
+    assert np.array_equal(ctx.table(9, 512).view(np.uint64), O.stream_log_table().view(np.uint64))
     sp = ctx.debug_eval(7, Ks)
     want = np.array([int(O.exp1_of_word(O.word(int(K), k + 1, 0)) * 2.0 ** 32) for k, K in enumerate(Ks)],
                     dtype=np.uint64)
