@@ -83,6 +83,10 @@ typedef struct {
   int kmax_refresh;   /* element batches between stop-limit refreshes (>= 1) */
   int blocks_per_cu;  /* persistent grid = CUs * this (0: occupancy limit) */
   double mini_expect; /* ProbMinHash1/3 elements expecting more points run as 8-lane mini-chains */
+  int split_log2;     /* batched forms: sets of >= 2^split_log2 elements are split into chunks of
+                         2^(split_log2-1) elements on separate workgroups (0: never; else 2..21).
+                         Needs out_keys, out_val or out_id, whose rows hold the merged keys. */
+  double c0_split;    /* extra margin added to c0 in the chunks' threshold */
 } pmh_tuning;
 
 /* Create a context for (seed, m, variant) on the current device.  variant is
@@ -164,17 +168,22 @@ int pmh_debug_eval(pmh_ctx* ctx, int what, const double* in, const uint64_t* in_
                    uint64_t* out_u, uint64_t n, void* stream);
 
 /* ---- serving: continuous batching of single-set requests ----------------
- * A dispatcher thread owned by the server admits queued requests into free
- * slots (a slot = stream + device buffers) as long as the slot's element
- * budget and the server's total HBM budget allow, copies them host->device,
- * runs the batched kernels and copies the signatures back.  Requests that
- * arrive while other batches are on the GPU are admitted as soon as a slot
- * frees; several slots run concurrently on separate streams.  Results are
- * identical to pmh_hash_sets on the same set. */
+ * The server owns `slots` execution slots (stream, pinned staging, device
+ * buffers).  One slot is open at a time: a submission copies its set into the
+ * open slot's pinned staging; a dispatcher thread launches the open slot as
+ * soon as it holds a request (copy in, heavy-first persistent kernel, copy the
+ * signatures out) and the next free slot opens, so requests that arrive while
+ * other batches are on the GPU form the next batch and run concurrently on
+ * their own stream.  Admission: at most slot_elems elements (never below
+ * 2^20, so any set fits) and slot_sets requests per slot; with a non-zero
+ * hbm_budget_bytes the slots' device buffers are sized to fit it; each
+ * slot's persistent grid is its share of the CUs' workgroup (LDS) capacity.
+ * When every slot is in flight a submission waits (back-pressure).  Results
+ * are identical to pmh_hash_sets on the same set. */
 int pmh_server_create(pmh_ctx* ctx, int slots, uint64_t slot_elems, uint32_t slot_sets,
                       uint64_t hbm_budget_bytes, pmh_server** out);
-/* Copy a request in ([host] ids, weights of n elements); *ticket receives its
- * handle.  PMH_ERR_BUSY when the pending queue is full. */
+/* Copy a request in ([host] ids, weights of n <= 2^20 elements); *ticket
+ * receives its handle.  Waits while every slot is in flight. */
 int pmh_server_submit(pmh_server* s, const uint64_t* ids, const double* weights, uint32_t n,
                       uint64_t* ticket);
 /* PMH_OK and the signature ([host] outputs of m entries, any may be NULL) when

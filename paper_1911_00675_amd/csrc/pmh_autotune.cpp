@@ -29,7 +29,8 @@ double time_once(pmh_ctx* c, const HashArgs& a, hipStream_t s, hipEvent_t e0, hi
 }
 
 double measure(pmh_ctx* c, const HashArgs& base, int trials, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int* rc) {
-  HashArgs a = make_args(c, base.ids, base.w, base.off, base.num_sets, nullptr, nullptr, nullptr, nullptr, &c->work);
+  HashArgs a = make_args(c, base.ids, base.w, base.off, base.num_sets, nullptr, nullptr, nullptr, base.out_keys,
+                         &c->work);
   time_once(c, a, s, e0, e1, rc);  // warm-up
   if (*rc) return 1e30;
   std::vector<double> v;
@@ -52,14 +53,20 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
   hipStream_t s = (hipStream_t)stream;
   int rc = ensure_work(c, &c->work, num_sets);
   if (rc) return rc;
+  // key rows of the timed launches (also the merge rows of split sets)
+  uint64_t* kbuf = nullptr;
+  if (hipMalloc(&kbuf, num_sets * (uint64_t)c->m * sizeof(uint64_t)) != hipSuccess) return PMH_ERR_OOM;
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PMH_ERR_DEVICE;
-  HashArgs base = make_args(c, ids, w, off, num_sets, nullptr, nullptr, nullptr, nullptr, &c->work);
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(kbuf);
+    return PMH_ERR_DEVICE;
+  }
+  HashArgs base = make_args(c, ids, w, off, num_sets, nullptr, nullptr, nullptr, kbuf, &c->work);
   Tuning best = c->tune;
   double best_ms = measure(c, base, trials, s, e0, e1, &rc);
   // coordinate descent, one knob at a time, two sweeps
   for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
-    for (int knob = 0; knob < 6 && !rc; ++knob) {
+    for (int knob = 0; knob < 7 && !rc; ++knob) {
       std::vector<Tuning> cands;
       auto add = [&](auto setter) {
         Tuning t = best;
@@ -87,10 +94,13 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
         case 5:
           for (int bp : {0, 1, 2, 4, 8}) add([&](Tuning& t) { t.blocks_per_cu = bp; });
           break;
+        case 6:
+          for (int sl : {0, 12, 13, 14, 15, 16, 17}) add([&](Tuning& t) { t.split_log2 = sl; });
+          break;
       }
       for (const Tuning& t : cands) {
         c->tune = t;
-        base = make_args(c, ids, w, off, num_sets, nullptr, nullptr, nullptr, nullptr, &c->work);
+        base = make_args(c, ids, w, off, num_sets, nullptr, nullptr, nullptr, kbuf, &c->work);
         const double ms = measure(c, base, trials, s, e0, e1, &rc);
         if (rc) break;
         if (ms < best_ms * 0.98) {
@@ -104,6 +114,8 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
   c->tune_version++;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(kbuf);
   if (best_out) {
     best_out->c0 = best.c0;
     best_out->grow = best.grow;
@@ -114,6 +126,8 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
     best_out->kmax_refresh = best.kmax_refresh;
     best_out->blocks_per_cu = best.blocks_per_cu;
     best_out->mini_expect = best.mini_expect;
+    best_out->split_log2 = best.split_log2;
+    best_out->c0_split = best.c0_split;
   }
   return rc;
 }

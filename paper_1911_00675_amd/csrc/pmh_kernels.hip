@@ -646,111 +646,138 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
 }
 
 // ------------------------------------------------------------- one set
-template <int V, int NW>
-__device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
-                            uint16_t* fy, const LogCell* lt, Shared& sm) {
-  constexpr int BS = NW * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint32_t m = A.m;
+// Per-set registers and LDS initialisation shared by whole sets and chunks.
+template <int NW>
+__device__ __forceinline__ Round set_round(const HashArgs& A, uint64_t set, uint32_t qcap, const LogCell* lt,
+                                           Shared& sm) {
+  const int tid = threadIdx.x;
   const uint64_t a = A.off[set], b = A.off[set + 1];
   const uint64_t n64 = b - a;
   Round R;
   R.ids = A.ids + a;
   R.w = A.w + a;
   R.n = (uint32_t)(n64 > kMaxSet ? 0 : n64);
-  R.m = m;
+  R.m = A.m;
   R.imax = A.imax;
   R.qcap = qcap;
   R.K0 = A.seedhash;
   R.lt = lt;
+  R.T = R.Tprev = 0.0;
   if (n64 > kMaxSet && tid == 0) atomicOr(A.status, kStatusSetTooLarge);
-
 #ifdef PMH_STATS
   if (tid < 16) sm.st[tid] = 0;
   __syncthreads();
   if (tid == 0) PMH_STAT(sm, kStSets, 1);
 #endif
-  for (uint32_t k = tid; k < m; k += BS) keys[k] = kEmptyKey;
-  // total weight (first threshold) and weight validation
+  return R;
+}
+
+// Sum of the valid weights of elements [p0, p1); flags invalid weights.
+template <int NW>
+__device__ double block_weight_sum(const HashArgs& A, const Round& R, uint32_t p0, uint32_t p1, Shared& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double ws = 0.0;
   bool bad = false;
-  for (uint32_t p = tid; p < R.n; p += BS) {
+  for (uint32_t p = p0 + tid; p < p1; p += NW * 64) {
     const double w = R.w[p];
     if (weight_ok(w)) ws += w;
     else if (w != 0.0) bad = true;
   }
   ws = wave_sum_f64(ws);
+  __syncthreads();  // red_d may still be read by an earlier reduction
   if (lane == 0) sm.red_d[wv] = ws;
   if (bad) atomicOr(A.status, kStatusWeight);
   __syncthreads();
   double W = 0.0;
   for (int i = 0; i < NW; ++i) W += sm.red_d[i];
+  return W;
+}
 
-  if (W > 0.0) {
-    double T = (double)m * (log((double)m) + A.c0) / W;
-    double Tprev = 0.0;
-    uint64_t kmax_round = kEmptyKey;
-    for (int round = 0;; ++round) {
-      const bool last = round + 1 >= A.max_rounds || !(T < DBL_MAX) || !(T > 0.0);
-      R.T = last ? __longlong_as_double(0x7FF0000000000000ll) : T;
-      R.Tprev = Tprev;
-      if (tid == 0) {
-        sm.kmax = kmax_round;
-        sm.qhead = sm.qtail = 0;
-        sm.mhead = sm.mtail = 0;
-        PMH_STAT(sm, kStRounds, 1);
-      }
-      __syncthreads();
-      const uint32_t batch = kEpt * BS;
-      for (uint32_t base = 0, nb = 0; base < R.n; base += batch, ++nb) {
-        const uint64_t kmax = shared_kmax(sm);
-#pragma unroll
-        for (uint32_t k = 0; k < kEpt; ++k) {
-          const uint32_t p = base + k * BS + tid;
-          if (p >= R.n) break;
-          const double w = R.w[p];
-          if (!weight_ok(w)) continue;
-          PMH_STAT(sm, kStElems, 1);
-          const double lam = w * R.T;  // expected points below T
-          if (lam > A.chain_expect) {
-            push_long(sm, q, p, 1, 0);
-            continue;
-          }
-          if ((V == 1 || V == 3) && lam > A.mini_expect) {
-            push_mini(sm, q, qcap, p, 1, 0);
-            continue;
-          }
-          const double winv = 1.0 / w;
-          const uint64_t K = mix64(R.ids[p] ^ R.K0);
-          const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
-#ifdef PMH_STATS
-          // wave-level cost of this element slot: the longest lane
-          int mx = steps;
-          for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
-          if (lane == __builtin_ctzll(__ballot(true))) PMH_STAT(sm, kStLaneIters, mx);
-#else
-          (void)steps;
-#endif
-        }
-        __syncthreads();
-        const uint32_t qt = sm.qtail + sm.mtail;  // read by every thread before anyone pushes again
-        __syncthreads();
-        const bool flush = qt + batch > qcap;
-        if (flush && tid == 0) PMH_STAT(sm, kStFlush, 1);
-        if (flush) chain_pass<V, NW>(A, R, keys, q, fy, sm);
-        if (flush || (nb % (uint32_t)A.kmax_refresh) == (uint32_t)A.kmax_refresh - 1) block_max_keys<NW>(keys, m, sm);
-      }
-      __syncthreads();
-      chain_pass<V, NW>(A, R, keys, q, fy, sm);
-      const uint64_t K = block_max_keys<NW>(keys, m, sm);
-      if (last || K < make_key(R.T, 0)) break;
-      Tprev = R.T;
-      T = R.T * A.grow;
-      kmax_round = K;
-    }
+// One round over elements [p0, p1): every point below R.T is generated and
+// the ones that can still lower a key are applied (stop limit kmax_start at
+// entry, refreshed as keys fall).  Returns the block max of the keys.
+template <int V, int NW>
+__device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, uint32_t p1, uint64_t kmax_start,
+                               uint64_t* keys, ChainEntry* q, uint16_t* fy, Shared& sm) {
+  constexpr int BS = NW * 64;
+  const int tid = threadIdx.x;
+  const uint32_t m = R.m, qcap = R.qcap;
+  if (tid == 0) {
+    sm.kmax = kmax_start;
+    sm.qhead = sm.qtail = 0;
+    sm.mhead = sm.mtail = 0;
+    PMH_STAT(sm, kStRounds, 1);
   }
   __syncthreads();
-  // epilogue: keys -> (position, value, id)
+  const uint32_t batch = kEpt * BS;
+  for (uint32_t base = p0, nb = 0; base < p1; base += batch, ++nb) {
+    const uint64_t kmax = shared_kmax(sm);
+#pragma unroll
+    for (uint32_t k = 0; k < kEpt; ++k) {
+      const uint32_t p = base + k * BS + tid;
+      if (p >= p1) break;
+      const double w = R.w[p];
+      if (!weight_ok(w)) continue;
+      PMH_STAT(sm, kStElems, 1);
+      const double lam = w * R.T;  // expected points below T
+      if (lam > A.chain_expect) {
+        push_long(sm, q, p, 1, 0);
+        continue;
+      }
+      if ((V == 1 || V == 3) && lam > A.mini_expect) {
+        push_mini(sm, q, qcap, p, 1, 0);
+        continue;
+      }
+      const double winv = 1.0 / w;
+      const uint64_t K = mix64(R.ids[p] ^ R.K0);
+      const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
+#ifdef PMH_STATS
+      // wave-level cost of this element slot: the longest lane
+      int mx = steps;
+      for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+      if ((threadIdx.x & 63) == __builtin_ctzll(__ballot(true))) PMH_STAT(sm, kStLaneIters, mx);
+#else
+      (void)steps;
+#endif
+    }
+    __syncthreads();
+    const uint32_t qt = sm.qtail + sm.mtail;  // read by every thread before anyone pushes again
+    __syncthreads();
+    const bool flush = qt + batch > qcap;
+    if (flush && tid == 0) PMH_STAT(sm, kStFlush, 1);
+    if (flush) chain_pass<V, NW>(A, R, keys, q, fy, sm);
+    if (flush || (nb % (uint32_t)A.kmax_refresh) == (uint32_t)A.kmax_refresh - 1) block_max_keys<NW>(keys, m, sm);
+  }
+  __syncthreads();
+  chain_pass<V, NW>(A, R, keys, q, fy, sm);
+  return block_max_keys<NW>(keys, m, sm);
+}
+
+// Rounds of growing thresholds over the whole set until every key is final
+// (keys must hold the set's current minima on entry).
+template <int V, int NW>
+__device__ void set_rounds(const HashArgs& A, Round& R, double T, uint64_t kmax_round, uint64_t* keys,
+                           ChainEntry* q, uint16_t* fy, Shared& sm) {
+  double Tprev = 0.0;
+  for (int round = 0;; ++round) {
+    const bool last = round + 1 >= A.max_rounds || !(T < DBL_MAX) || !(T > 0.0);
+    R.T = last ? __longlong_as_double(0x7FF0000000000000ll) : T;
+    R.Tprev = Tprev;
+    const uint64_t K = round_pass<V, NW>(A, R, 0, R.n, kmax_round, keys, q, fy, sm);
+    if (last || K < make_key(R.T, 0)) break;
+    Tprev = R.T;
+    T = R.T * A.grow;
+    kmax_round = K;
+  }
+}
+
+// keys (LDS) -> (position, value, id) of the set's signature.
+template <int NW>
+__device__ void epilogue(const HashArgs& A, const Round& R, uint64_t set, const uint64_t* keys, Shared& sm) {
+  constexpr int BS = NW * 64;
+  const int tid = threadIdx.x;
+  const uint32_t m = R.m;
+  __syncthreads();
   const uint64_t o = set * (uint64_t)m;
   for (uint32_t k = tid; k < m; k += BS) {
     const uint64_t key = keys[k];
@@ -766,6 +793,70 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
 #ifdef PMH_STATS
   if (tid < kStCount && A.points) atomicAdd((unsigned long long*)&A.points[tid], (unsigned long long)sm.st[tid]);
 #endif
+}
+
+template <int V, int NW>
+__device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
+                            uint16_t* fy, const LogCell* lt, Shared& sm) {
+  Round R = set_round<NW>(A, set, qcap, lt, sm);
+  for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = kEmptyKey;
+  const double W = block_weight_sum<NW>(A, R, 0, R.n, sm);
+  if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, kEmptyKey, keys, q, fy, sm);
+  epilogue<NW>(A, R, set, keys, sm);
+}
+
+// One chunk of a set split across workgroups.  The chunk generates every
+// point below its own threshold T_c (from its weight sum scaled to the whole
+// set), merges its keys into the set's global keys with a 64-bit atomic min,
+// and lowers the set's smallest threshold.  The last chunk to finish checks
+// that every merged key lies below that smallest threshold (then all are
+// final: every point below it has been applied); otherwise it completes the
+// set with an unbounded round.  It then writes the epilogue.
+template <int V, int NW>
+__device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uint32_t chunk, uint32_t nchunks,
+                              uint64_t* keys, ChainEntry* q, uint32_t qcap, uint16_t* fy, const LogCell* lt,
+                              Shared& sm) {
+  constexpr int BS = NW * 64;
+  const int tid = threadIdx.x;
+  Round R = set_round<NW>(A, set, qcap, lt, sm);
+  const uint32_t m = R.m;
+  const uint32_t csize = 1u << (A.split_log2 - 1);
+  const uint32_t p0 = chunk * csize, p1 = p0 + csize < R.n ? p0 + csize : R.n;
+  uint64_t* gk = A.big_keys + set * (uint64_t)m;
+  unsigned long long* done = (unsigned long long*)&A.big_state[2 * (uint64_t)big];
+  unsigned long long* tmin = (unsigned long long*)&A.big_state[2 * (uint64_t)big + 1];
+  for (uint32_t k = tid; k < m; k += BS) keys[k] = kEmptyKey;
+  const double Wc = block_weight_sum<NW>(A, R, p0, p1, sm);
+  if (Wc > 0.0) {
+    const double West = Wc * ((double)R.n / (double)(p1 - p0));
+    const double T = (double)m * (log((double)m) + A.c0 + A.c0_split) / West;
+    R.T = T > 0.0 ? T : __longlong_as_double(0x7FF0000000000000ll);
+    R.Tprev = 0.0;
+    round_pass<V, NW>(A, R, p0, p1, kEmptyKey, keys, q, fy, sm);
+    for (uint32_t k = tid; k < m; k += BS)
+      if (keys[k] != kEmptyKey) atomicMin((unsigned long long*)&gk[k], (unsigned long long)keys[k]);
+    if (tid == 0) atomicMin(tmin, (unsigned long long)__double_as_longlong(R.T));
+  }
+  __threadfence();  // this workgroup's merges before its completion count
+  __syncthreads();
+  if (tid == 0) {
+    sm.item = atomicAdd(done, 1ull) + 1 == nchunks ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!sm.item) return;
+  __threadfence();
+  for (uint32_t k = tid; k < m; k += BS)
+    keys[k] = __hip_atomic_load(&gk[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double Tmin = __longlong_as_double((long long)__hip_atomic_load(tmin, __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_AGENT));
+  __syncthreads();
+  const uint64_t K = block_max_keys<NW>(keys, m, sm);
+  if (!(K < make_key(Tmin, 0))) {  // some label not covered below the smallest threshold
+    R.T = __longlong_as_double(0x7FF0000000000000ll);
+    R.Tprev = Tmin;  // every point below Tmin has been merged
+    round_pass<V, NW>(A, R, 0, R.n, K, keys, q, fy, sm);
+  }
+  epilogue<NW>(A, R, set, keys, sm);
 }
 
 // Dynamic LDS: log table (256 cells) | keys[m] | chain queue | Fisher-Yates arrays.
@@ -787,22 +878,44 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
   __syncthreads();
 }
 
+// Persistent grid.  Work items: first the chunks of the split sets (heavy
+// first), then one item per remaining set.  meta = {split sets, chunk items,
+// total items}, written by k_order.
 template <int V, int NW>
 __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
   __shared__ Shared sm;
+  __shared__ uint32_t job[4];
   LogCell* lt;
   uint64_t* keys;
   ChainEntry* q;
   uint32_t qcap;
   uint16_t* fy;
   carve<V, NW>(A, lt, keys, q, qcap, fy);
+  const uint32_t num_big = A.meta[0], vbig = A.meta[1], total = A.meta[2];
   for (;;) {
-    if (threadIdx.x == 0) sm.item = atomicAdd(A.counter, 1u);
+    if (threadIdx.x == 0) {
+      const uint32_t v = atomicAdd(A.counter, 1u);
+      job[0] = v;
+      if (v < vbig) {  // chunk of a split set: find b with prefix[b] <= v < prefix[b+1]
+        uint32_t lo = 0, hi = num_big;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (A.big_prefix[mid] <= v) lo = mid;
+          else hi = mid;
+        }
+        job[1] = lo;
+        job[2] = v - A.big_prefix[lo];
+        job[3] = A.big_prefix[lo + 1] - A.big_prefix[lo];
+      } else if (v < total) {
+        job[1] = num_big + (v - vbig);
+      }
+    }
     __syncthreads();
-    const uint32_t item = sm.item;
+    const uint32_t v = job[0], j1 = job[1], j2 = job[2], j3 = job[3];
     __syncthreads();
-    if (item >= A.num_items) break;
-    process_set<V, NW>(A, A.order ? A.order[item] : item, keys, q, qcap, fy, lt, sm);
+    if (v >= total) break;
+    if (v < vbig) process_chunk<V, NW>(A, A.order[j1], j1, j2, j3, keys, q, qcap, fy, lt, sm);
+    else process_set<V, NW>(A, A.order[j1], keys, q, qcap, fy, lt, sm);
   }
 }
 
@@ -820,11 +933,17 @@ __global__ __launch_bounds__(NW * 64) void k_hash_one(HashArgs A, uint64_t set) 
 
 // ------------------------------------------------------ heavy-first order
 // One workgroup: counting sort of the sets by size class (bit length of n),
-// largest class first; also resets the persistent work counter.
-__global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t num_sets, uint32_t* order,
-                                                uint32_t* counter, uint32_t* status) {
+// largest class first (oversize sets last); sets with n >= 2^split_log2 are
+// split into chunks of 2^(split_log2-1) elements: their chunk counts are
+// prefix-summed into big_prefix and their state reset.  Also resets the
+// persistent work counter and writes meta.
+__global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t num_sets, uint32_t split_log2,
+                                                uint32_t* order, uint32_t* counter, uint32_t* meta,
+                                                uint32_t* big_prefix, uint64_t* big_state, uint32_t* status) {
   __shared__ uint32_t cnt[24];
   __shared__ uint32_t pos[24];
+  __shared__ uint32_t scan[1024];
+  __shared__ uint32_t carry, num_big_s;
   const int tid = threadIdx.x;
   if (tid < 24) cnt[tid] = 0;
   __syncthreads();
@@ -836,11 +955,19 @@ __global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t nu
   __syncthreads();
   if (tid == 0) {
     uint32_t acc = 0;
-    for (int c = 23; c >= 0; --c) {
+    for (int c = 21; c >= 0; --c) {
       pos[c] = acc;
       acc += cnt[c];
     }
+    pos[22] = acc;
+    pos[23] = acc;
+    uint32_t nb = 0;
+    if (split_log2 > 0)
+      for (uint32_t c = split_log2 + 1; c <= 21; ++c) nb += cnt[c];
+    meta[0] = nb;
+    num_big_s = nb;
     *counter = 0;
+    carry = 0;
     if (cnt[23]) atomicOr(status, kStatusSetTooLarge);
   }
   __syncthreads();
@@ -848,6 +975,48 @@ __global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t nu
     const uint64_t n = off[s + 1] - off[s];
     const uint32_t c = n > kMaxSet ? 23u : (n ? 64u - (uint32_t)__builtin_clzll(n) : 0u);
     order[atomicAdd(&pos[c], 1u)] = (uint32_t)s;
+  }
+  __syncthreads();
+  // chunk counts of the split sets (they occupy order[0 .. num_big))
+  const uint32_t num_big = num_big_s;
+  const uint32_t csize_log2 = split_log2 > 0 ? split_log2 - 1 : 0;
+  for (uint32_t b0 = 0; b0 < num_big; b0 += 1024) {
+    const uint32_t b = b0 + tid;
+    uint32_t c = 0;
+    if (b < num_big) {
+      const uint32_t s = order[b];
+      const uint64_t n = off[s + 1] - off[s];
+      c = (uint32_t)((n + (1ull << csize_log2) - 1) >> csize_log2);
+      big_state[2 * (uint64_t)b] = 0;                        // chunks done
+      big_state[2 * (uint64_t)b + 1] = 0x7FF0000000000000ull;  // smallest threshold (+inf)
+    }
+    scan[tid] = c;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan
+      const uint32_t x = tid >= d ? scan[tid - d] : 0u;
+      __syncthreads();
+      scan[tid] += x;
+      __syncthreads();
+    }
+    if (b < num_big) big_prefix[b + 1] = carry + scan[tid];
+    __syncthreads();
+    if (tid == 0) carry += scan[1023];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    big_prefix[0] = 0;
+    meta[1] = carry;                                  // chunk items
+    meta[2] = carry + (uint32_t)(num_sets - num_big);  // all items
+  }
+}
+
+// Global keys of the split sets start empty.
+__global__ __launch_bounds__(256) void k_big_init(const uint32_t* order, const uint32_t* meta, uint32_t m,
+                                                  uint64_t* big_keys) {
+  const uint64_t total = (uint64_t)meta[0] * m;
+  for (uint64_t e = blockIdx.x * 256ull + threadIdx.x; e < total; e += (uint64_t)gridDim.x * 256) {
+    const uint64_t b = e / m, k = e % m;
+    big_keys[(uint64_t)order[b] * m + k] = kEmptyKey;
   }
 }
 
@@ -1044,9 +1213,15 @@ hipError_t occupancy(int variant, int waves, size_t lds, int* blocks_per_cu) {
   PMH_DISPATCH(occ_t, lds, blocks_per_cu)
 }
 
-hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t* order, uint32_t* counter,
+hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t split_log2, const WorkArgs& w,
                         uint32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, off, num_sets, order, counter, status);
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, off, num_sets, split_log2, w.order, w.counter, w.meta,
+                     w.big_prefix, w.big_state, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_init(const WorkArgs& w, uint32_t m, uint64_t* big_keys, hipStream_t s) {
+  hipLaunchKernelGGL(k_big_init, dim3(512), dim3(256), 0, s, w.order, w.meta, m, big_keys);
   return hipGetLastError();
 }
 

@@ -51,17 +51,28 @@ int effective_waves(const pmh_ctx* c) {
   return w;
 }
 
+void free_work(WorkBuf* wb) {
+  if (wb->order) (void)hipFree(wb->order);
+  if (wb->small) (void)hipFree(wb->small);
+  if (wb->big_prefix) (void)hipFree(wb->big_prefix);
+  if (wb->big_state) (void)hipFree(wb->big_state);
+  *wb = WorkBuf{};
+}
+
 int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets) {
+  (void)c;
   if (wb->cap >= num_sets && wb->order) return PMH_OK;
   uint64_t cap = std::max<uint64_t>(num_sets, 1024);
   cap = std::max<uint64_t>(cap, wb->cap * 2);
-  if (wb->order) (void)hipFree(wb->order);
-  wb->order = nullptr;
-  wb->cap = 0;
-  if (hipMalloc(&wb->order, cap * sizeof(uint32_t)) != hipSuccess) return PMH_ERR_OOM;
+  free_work(wb);
+  if (hipMalloc(&wb->order, cap * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&wb->small, 8 * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&wb->big_prefix, (cap + 1) * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&wb->big_state, 2 * cap * sizeof(uint64_t)) != hipSuccess) {
+    free_work(wb);
+    return PMH_ERR_OOM;
+  }
   wb->cap = cap;
-  if (!wb->counter && hipMalloc(&wb->counter, sizeof(uint32_t) * 4) != hipSuccess) return PMH_ERR_OOM;
-  (void)c;
   return PMH_OK;
 }
 
@@ -89,24 +100,39 @@ HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const
   a.lane_budget = c->tune.lane_budget;
   a.kmax_refresh = c->tune.kmax_refresh;
   a.status = c->status;
-  a.order = wb ? wb->order : nullptr;
-  a.counter = wb ? wb->counter : nullptr;
+  if (wb) {
+    const WorkArgs wa = wb->args();
+    a.order = wa.order;
+    a.counter = wa.counter;
+    a.meta = wa.meta;
+    a.big_prefix = wa.big_prefix;
+    a.big_state = wa.big_state;
+  }
+  // A split set merges its chunks' keys in one of its own m-entry 64-bit
+  // output rows (overwritten by the signature at the end); without such an
+  // output no set is split.
+  a.big_keys = keys ? keys : val ? reinterpret_cast<uint64_t*>(val) : id;
+  a.split_log2 = a.big_keys ? (uint32_t)c->tune.split_log2 : 0u;
+  a.c0_split = c->tune.c0_split;
   a.num_items = (uint32_t)num_sets;
   a.points = c->stats;
   return a;
 }
 
-int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s) {
+int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, int per_cu, int waves) {
   if (a.num_sets == 0) return PMH_OK;
-  const int waves = effective_waves(c);
+  if (waves <= 0) waves = effective_waves(c);
   const size_t lds = lds_bytes(c->variant, c->m, waves);
-  int per_cu = c->tune.blocks_per_cu;
+  if (per_cu <= 0) per_cu = c->tune.blocks_per_cu;
   if (per_cu <= 0) {
     if (occupancy(c->variant, waves, lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
   }
-  uint64_t grid = (uint64_t)c->num_cu * (uint64_t)per_cu;
-  grid = std::min<uint64_t>(grid, a.num_sets);
-  if (launch_order(a.off, a.num_sets, wb->order, wb->counter, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
+  // a split set of at most 2^20 elements has at most 2^(21 - split_log2) chunks
+  const uint64_t items = a.split_log2 ? a.num_sets << (21 - a.split_log2) : a.num_sets;
+  const uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cu * (uint64_t)per_cu, items);
+  const WorkArgs wa = wb->args();
+  if (launch_order(a.off, a.num_sets, a.split_log2, wa, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (a.split_log2 && launch_big_init(wa, a.m, a.big_keys, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (launch_hash(c->variant, a, waves, (int)grid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
   return PMH_OK;
 }
@@ -208,8 +234,7 @@ void pmh_destroy(pmh_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  if (c->work.order) (void)hipFree(c->work.order);
-  if (c->work.counter) (void)hipFree(c->work.counter);
+  free_work(&c->work);
   if (c->table_mem) (void)hipFree(c->table_mem);
   if (c->status) (void)hipFree(c->status);
   if (c->stats) (void)hipFree(c->stats);
@@ -303,7 +328,8 @@ int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
   if (!c || !t) return PMH_ERR_ARG;
   if (!(t->grow > 1.0) || t->max_rounds < 1 || t->lane_budget < 1 || t->kmax_refresh < 1 ||
       (t->waves != 1 && t->waves != 2 && t->waves != 4) || t->blocks_per_cu < 0 || !(t->c0 > -100.0) ||
-      !(t->chain_expect >= 0.0) || !(t->mini_expect >= 0.0))
+      !(t->chain_expect >= 0.0) || !(t->mini_expect >= 0.0) || t->split_log2 < 0 || t->split_log2 == 1 ||
+      t->split_log2 > 21 || !(t->c0_split > -100.0) || !(t->c0_split < 1e6))
     return PMH_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->mu);
   c->tune.c0 = t->c0;
@@ -315,6 +341,8 @@ int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
   c->tune.kmax_refresh = t->kmax_refresh;
   c->tune.blocks_per_cu = t->blocks_per_cu;
   c->tune.mini_expect = t->mini_expect;
+  c->tune.split_log2 = t->split_log2;
+  c->tune.c0_split = t->c0_split;
   c->tune_version++;
   return PMH_OK;
 }
@@ -330,6 +358,8 @@ int pmh_get_tuning(const pmh_ctx* c, pmh_tuning* t) {
   t->kmax_refresh = c->tune.kmax_refresh;
   t->blocks_per_cu = c->tune.blocks_per_cu;
   t->mini_expect = c->tune.mini_expect;
+  t->split_log2 = c->tune.split_log2;
+  t->c0_split = c->tune.c0_split;
   return PMH_OK;
 }
 

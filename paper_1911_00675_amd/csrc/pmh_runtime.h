@@ -10,13 +10,17 @@
 
 namespace pmh {
 
-// Per-call device scratch: the heavy-first work list and the persistent
-// grid's work counter.
+// Per-call device scratch: the heavy-first work list, the persistent grid's
+// work counter and the split sets' chunk prefix and completion state.
 struct WorkBuf {
   uint32_t* order = nullptr;
-  uint32_t* counter = nullptr;
+  uint32_t* small = nullptr;  // [0]: work counter, [4..7]: meta
+  uint32_t* big_prefix = nullptr;
+  uint64_t* big_state = nullptr;
   uint64_t cap = 0;
+  WorkArgs args() const { return WorkArgs{order, small, small + 4, big_prefix, big_state}; }
 };
+void free_work(WorkBuf* wb);
 
 struct GraphKey {
   const void* ids;
@@ -75,5 +79,7 @@ int effective_waves(const pmh_ctx* c);
 int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets);
 HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
                    uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, const WorkBuf* wb);
-int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s);
+// Order kernel, split-set init and the persistent grid (per_cu workgroups per
+// CU and waves per workgroup from the tuning when 0).
+int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, int per_cu = 0, int waves = 0);
 }  // namespace pmh

@@ -62,7 +62,8 @@ class PmhError(RuntimeError):
 class pmh_tuning(ctypes.Structure):
     _fields_ = [("c0", ctypes.c_double), ("grow", ctypes.c_double), ("max_rounds", ctypes.c_int),
                 ("chain_expect", ctypes.c_double), ("lane_budget", ctypes.c_int), ("waves", ctypes.c_int),
-                ("kmax_refresh", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("mini_expect", ctypes.c_double)]
+                ("kmax_refresh", ctypes.c_int), ("blocks_per_cu", ctypes.c_int), ("mini_expect", ctypes.c_double),
+                ("split_log2", ctypes.c_int), ("c0_split", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

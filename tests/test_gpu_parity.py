@@ -228,6 +228,76 @@ def test_schedule_invariance(pmh, variant):
     ctx.close()
 
 
+def _split_batch(seed):
+    """Sets around the split thresholds, with empty sets and runs of zero
+    weights (chunks with nothing to hash)."""
+    rng = np.random.default_rng(seed)
+    sizes = [0, 1, 63, 64, 65, 200, 1000, 4097, 3, 20000, 129, 0, 5000]
+    n = sum(sizes)
+    ids = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64)
+    w = rng.pareto(1.5, size=n) + 0.05
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    w[off[7]:off[7] + 100] = 0.0  # a whole chunk and a part of the next without weight
+    w[off[12]:off[13]] = 0.0      # a split set without any weight
+    return W.Batch(ids, w, off)
+
+
+@pytest.mark.parametrize("variant,m", [(1, 64), (2, 64), (3, 64), (4, 64), (1, 1024), (3, 1024), (2, 300),
+                                       (4, 300), (1, 1), (2, 1)])
+def test_split_sets(pmh, variant, m):
+    """Sets split across workgroups (chunks merged by atomic min, completion
+    check, repair round) give the oracle's signature bit for bit, whichever
+    output row holds the merge and however often the repair runs."""
+    print(f"split sets PMH{variant} m={m}", flush=True)
+    b = _split_batch(40 + variant)
+    want = O.sign_batch(variant, SEED, m, b.ids, b.weights, b.offsets, nthreads=8)
+    decoded = [O.decode(want[s], b.set(s)[0]) for s in range(b.num_sets)]
+    ctx = pmh.Context(SEED, m, variant)
+    default = ctx.get_tuning().as_dict()
+    for cfg in (dict(split_log2=6), dict(split_log2=6, c0_split=-30.0), dict(split_log2=7, c0_split=40.0),
+                dict(split_log2=2), dict(split_log2=12), dict(split_log2=6, waves=1, blocks_per_cu=1)):
+        ctx.set_tuning(**cfg)
+        for outputs in (("idx", "val", "id", "keys"), ("val",), ("id", "idx"), ("idx",)):
+            for mode in ("batched", "graph"):
+                sig = ctx.hash_sets(_dev(b.ids), _dev(b.weights), _dev(b.offsets), mode=mode, outputs=outputs)
+                assert ctx.status() == pmh.PMH_OK
+                got = {k: getattr(sig, k).cpu().numpy() for k in outputs}
+                for s in range(b.num_sets):
+                    ri, rv, rid = decoded[s]
+                    if "keys" in got:
+                        assert np.array_equal(got["keys"][s].view(np.uint64), want[s]), (cfg, mode, s)
+                    if "idx" in got:
+                        assert np.array_equal(got["idx"][s].view(np.uint32), ri), (cfg, mode, outputs, s)
+                    if "val" in got:
+                        assert np.array_equal(got["val"][s].view(np.uint64), rv.view(np.uint64)), (cfg, mode, s)
+                    if "id" in got:
+                        assert np.array_equal(got["id"][s].view(np.uint64), rid), (cfg, mode, outputs, s)
+        ctx.set_tuning(**default)
+    ctx.close()
+
+
+def test_split_largest_set(pmh):
+    """One set of 2^20 elements (the largest accepted) with the default split,
+    alone and beside small sets."""
+    print("split: 2^20-element set", flush=True)
+    rng = np.random.default_rng(11)
+    n = 1 << 20
+    sizes = [5, n, 17]
+    ids = rng.integers(0, 2**64 - 1, size=sum(sizes), dtype=np.uint64)
+    w = rng.exponential(size=sum(sizes))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    b = W.Batch(ids, w, off)
+    for variant, m in ((1, 1024), (4, 256)):
+        want = O.sign_batch(variant, SEED, m, ids, w, off, nthreads=8)
+        ctx = pmh.Context(SEED, m, variant)
+        sig, st = _keys(ctx, b)
+        assert st == pmh.PMH_OK
+        assert np.array_equal(_host(sig)[0], want)
+        sig, st = _keys(ctx, b.subset([1]))
+        assert st == pmh.PMH_OK and np.array_equal(_host(sig)[0][0], want[1])
+        ctx.close()
+
+
 def test_alone_and_in_a_mix(pmh):
     """A set's signature is the same alone, in any batch, at any position."""
     print("alone vs mix", flush=True)
