@@ -43,16 +43,16 @@ struct Tuning {
   int blocks_per_cu = 0;    // persistent grid = CUs * this (0: occupancy limit)
   double mini_expect = 3;   // ProbMinHash1/3 elements expecting more points run as 8-lane mini-chains
   int split_log2 = 15;      // sets of >= 2^this elements run as chunks of 2^(this-1) (0: never split)
-  double c0_split = 3.0;    // extra threshold margin of chunks (keeps the completion repair rare)
+  double c0_split = 6.0;    // extra threshold margin of chunks (keeps the completion repair rare)
 };
 
 // Device scratch of one batched launch (allocated by the runtime).
 struct WorkArgs {
   uint32_t* order;       // [num_sets] heavy-first set order
-  uint32_t* counter;     // persistent work counter
+  uint32_t* counter;     // [2]: work counters of the persistent and the finish grid
   uint32_t* meta;        // [4]: split sets, chunk items, all items
   uint32_t* big_prefix;  // [num_sets + 1] chunk prefix of the split sets
-  uint64_t* big_state;   // [2 num_sets] per split set: chunks done, smallest threshold bits
+  uint64_t* big_state;   // [num_sets] per split set: smallest chunk threshold (bits)
 };
 
 struct HashArgs {
@@ -72,7 +72,7 @@ struct HashArgs {
   int max_rounds, lane_budget, kmax_refresh;
   uint32_t* status;          // device status word
   const uint32_t* order;     // work list (set indices), heavy first
-  uint32_t* counter;         // persistent work counter (zeroed by the order kernel)
+  uint32_t* counter;         // work counters (zeroed by the order kernel)
   const uint32_t* meta;      // split sets, chunk items, all items (written by the order kernel)
   const uint32_t* big_prefix;
   uint64_t* big_state;
@@ -88,6 +88,7 @@ hipError_t launch_init_tables(int variant, uint32_t m, Tables t, hipStream_t s);
 hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t split_log2, const WorkArgs& w,
                         uint32_t* status, hipStream_t s);
 hipError_t launch_big_init(const WorkArgs& w, uint32_t m, uint64_t* big_keys, hipStream_t s);
+hipError_t launch_big_finish(int variant, const HashArgs& a, int waves, int grid, size_t lds, hipStream_t s);
 hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size_t lds,
                        hipStream_t s);
 hipError_t launch_hash_one(int variant, const HashArgs& a, uint64_t set, int waves, size_t lds,

@@ -49,7 +49,7 @@ constexpr uint32_t kEpt = 2;                     // elements per thread per batc
 #define PMH_STAT(sm, i, v) ((void)0)
 #endif
 enum { kStSets, kStRounds, kStElems, kStLanePts, kStLaneIters, kStLaneApply, kStMiniSteps, kStMiniPts,
-       kStMiniElems, kStChainTiles, kStChainPts, kStChainElems, kStFlush, kStBlockMax, kStApply, kStCount };
+       kStMiniElems, kStChainTiles, kStChainPts, kStChainElems, kStFlush, kStBlockMax, kStApply, kStRepairs, kStCount };
 
 // ---------------------------------------------------------------- randomness
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -411,17 +411,16 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
 }
 
 // ------------------------------------------------------------ chain mode
-// One wavefront runs one element's stream, 64 consecutive points per step.
+// One wavefront runs one element's stream, 64 consecutive points per step,
+// until a point reaches R.T or the stop limit.
 template <int V>
-__device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, uint64_t* keys, uint16_t* g,
-                           Shared& sm) {
+__device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, double winv, uint64_t K,
+                           uint64_t* keys, uint16_t* g, Shared& sm) {
   const Tables& t = A.t;
   const int lane = threadIdx.x & 63;
   const uint32_t m = R.m;
   const LogCell* lt = R.lt;
   const uint32_t p = e.p;
-  const double winv = 1.0 / R.w[p];
-  const uint64_t K = mix64(R.ids[p] ^ R.K0);
   const uint32_t end = (V == 2 || V == 4) ? m : R.imax;
   uint64_t kmax = shared_kmax(sm);
   uint32_t i0 = e.i;
@@ -627,14 +626,15 @@ template <int V, int NW>
 __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, ChainEntry* q, uint16_t* fy,
                            Shared& sm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint16_t* g = fy ? fy + (size_t)wv * R.m : nullptr;
+  uint16_t* g = (V == 2 || V == 4) ? fy + (size_t)wv * R.m : nullptr;
   const uint32_t qtail = sm.qtail;
   for (;;) {  // long streams first
     uint32_t e = 0;
     if (lane == 0) e = atomicAdd(&sm.qhead, 1u);
     e = (uint32_t)__shfl((int)e, 0);
     if (e >= qtail) break;
-    chain_elem<V>(A, R, q[e], keys, g, sm);
+    const ChainEntry ce = q[e];
+    chain_elem<V>(A, R, ce, 1.0 / R.w[ce.p], mix64(R.ids[ce.p] ^ R.K0), keys, g, sm);
   }
   if constexpr (V == 1 || V == 3) mini_pass<V>(A, R, keys, q, sm);
   __syncthreads();
@@ -712,6 +712,10 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
   const uint32_t batch = kEpt * BS;
   for (uint32_t base = p0, nb = 0; base < p1; base += batch, ++nb) {
     const uint64_t kmax = shared_kmax(sm);
+    // points above the stop limit's value are never generated: the expected
+    // count of an element is its weight times the smaller of T and that value
+    const double Tk = kmax == kEmptyKey ? R.T : __longlong_as_double((long long)(kmax & ~kPosMask));
+    const double Teff = Tk < R.T ? Tk : R.T;
 #pragma unroll
     for (uint32_t k = 0; k < kEpt; ++k) {
       const uint32_t p = base + k * BS + tid;
@@ -719,7 +723,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
       const double w = R.w[p];
       if (!weight_ok(w)) continue;
       PMH_STAT(sm, kStElems, 1);
-      const double lam = w * R.T;  // expected points below T
+      const double lam = w * Teff;  // expected points generated
       if (lam > A.chain_expect) {
         push_long(sm, q, p, 1, 0);
         continue;
@@ -754,11 +758,11 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
 }
 
 // Rounds of growing thresholds over the whole set until every key is final
-// (keys must hold the set's current minima on entry).
+// (keys must hold the set's current minima on entry, with every point below
+// Tprev applied).
 template <int V, int NW>
-__device__ void set_rounds(const HashArgs& A, Round& R, double T, uint64_t kmax_round, uint64_t* keys,
-                           ChainEntry* q, uint16_t* fy, Shared& sm) {
-  double Tprev = 0.0;
+__device__ void set_rounds(const HashArgs& A, Round& R, double T, double Tprev, uint64_t kmax_round,
+                           uint64_t* keys, ChainEntry* q, uint16_t* fy, Shared& sm) {
   for (int round = 0;; ++round) {
     const bool last = round + 1 >= A.max_rounds || !(T < DBL_MAX) || !(T > 0.0);
     R.T = last ? __longlong_as_double(0x7FF0000000000000ll) : T;
@@ -801,21 +805,18 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
   Round R = set_round<NW>(A, set, qcap, lt, sm);
   for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = kEmptyKey;
   const double W = block_weight_sum<NW>(A, R, 0, R.n, sm);
-  if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, kEmptyKey, keys, q, fy, sm);
+  if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kEmptyKey, keys, q, fy, sm);
   epilogue<NW>(A, R, set, keys, sm);
 }
 
 // One chunk of a set split across workgroups.  The chunk generates every
 // point below its own threshold T_c (from its weight sum scaled to the whole
-// set), merges its keys into the set's global keys with a 64-bit atomic min,
-// and lowers the set's smallest threshold.  The last chunk to finish checks
-// that every merged key lies below that smallest threshold (then all are
-// final: every point below it has been applied); otherwise it completes the
-// set with an unbounded round.  It then writes the epilogue.
+// set), merges its keys into the set's merge row with a 64-bit atomic min and
+// lowers the set's smallest threshold.  Finishing the set is left to
+// k_big_finish, after the kernel boundary has made every merge visible.
 template <int V, int NW>
-__device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uint32_t chunk, uint32_t nchunks,
-                              uint64_t* keys, ChainEntry* q, uint32_t qcap, uint16_t* fy, const LogCell* lt,
-                              Shared& sm) {
+__device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uint32_t chunk, uint64_t* keys,
+                              ChainEntry* q, uint32_t qcap, uint16_t* fy, const LogCell* lt, Shared& sm) {
   constexpr int BS = NW * 64;
   const int tid = threadIdx.x;
   Round R = set_round<NW>(A, set, qcap, lt, sm);
@@ -823,8 +824,6 @@ __device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uin
   const uint32_t csize = 1u << (A.split_log2 - 1);
   const uint32_t p0 = chunk * csize, p1 = p0 + csize < R.n ? p0 + csize : R.n;
   uint64_t* gk = A.big_keys + set * (uint64_t)m;
-  unsigned long long* done = (unsigned long long*)&A.big_state[2 * (uint64_t)big];
-  unsigned long long* tmin = (unsigned long long*)&A.big_state[2 * (uint64_t)big + 1];
   for (uint32_t k = tid; k < m; k += BS) keys[k] = kEmptyKey;
   const double Wc = block_weight_sum<NW>(A, R, p0, p1, sm);
   if (Wc > 0.0) {
@@ -835,26 +834,31 @@ __device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uin
     round_pass<V, NW>(A, R, p0, p1, kEmptyKey, keys, q, fy, sm);
     for (uint32_t k = tid; k < m; k += BS)
       if (keys[k] != kEmptyKey) atomicMin((unsigned long long*)&gk[k], (unsigned long long)keys[k]);
-    if (tid == 0) atomicMin(tmin, (unsigned long long)__double_as_longlong(R.T));
-  }
-  __threadfence();  // this workgroup's merges before its completion count
-  __syncthreads();
-  if (tid == 0) {
-    sm.item = atomicAdd(done, 1ull) + 1 == nchunks ? 1u : 0u;
+    if (tid == 0) atomicMin((unsigned long long*)&A.big_state[big], (unsigned long long)__double_as_longlong(R.T));
   }
   __syncthreads();
-  if (!sm.item) return;
-  __threadfence();
-  for (uint32_t k = tid; k < m; k += BS)
-    keys[k] = __hip_atomic_load(&gk[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double Tmin = __longlong_as_double((long long)__hip_atomic_load(tmin, __ATOMIC_RELAXED,
-                                                                          __HIP_MEMORY_SCOPE_AGENT));
+#ifdef PMH_STATS
+  if (tid < kStCount && A.points) atomicAdd((unsigned long long*)&A.points[tid], (unsigned long long)sm.st[tid]);
+#endif
+}
+
+// Completion of a split set: every merged key below the smallest chunk
+// threshold Tmin is final (all points below Tmin were applied); otherwise one
+// unbounded round over the whole set finishes it.  Then the epilogue.
+template <int V, int NW>
+__device__ void finish_set(const HashArgs& A, uint64_t set, uint32_t big, uint64_t* keys, ChainEntry* q,
+                           uint32_t qcap, uint16_t* fy, const LogCell* lt, Shared& sm) {
+  const int tid = threadIdx.x;
+  Round R = set_round<NW>(A, set, qcap, lt, sm);
+  const uint32_t m = R.m;
+  const uint64_t* gk = A.big_keys + set * (uint64_t)m;
+  for (uint32_t k = tid; k < m; k += NW * 64) keys[k] = gk[k];
+  const double Tmin = __longlong_as_double((long long)A.big_state[big]);
   __syncthreads();
   const uint64_t K = block_max_keys<NW>(keys, m, sm);
-  if (!(K < make_key(Tmin, 0))) {  // some label not covered below the smallest threshold
-    R.T = __longlong_as_double(0x7FF0000000000000ll);
-    R.Tprev = Tmin;  // every point below Tmin has been merged
-    round_pass<V, NW>(A, R, 0, R.n, K, keys, q, fy, sm);
+  if (!(K < make_key(Tmin, 0))) {  // some label not covered below the smallest threshold:
+    if (tid == 0) PMH_STAT(sm, kStRepairs, 1);  // more rounds over the whole set, above Tmin
+    set_rounds<V, NW>(A, R, Tmin * A.grow, Tmin, K, keys, q, fy, sm);
   }
   epilogue<NW>(A, R, set, keys, sm);
 }
@@ -884,7 +888,7 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
 template <int V, int NW>
 __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
   __shared__ Shared sm;
-  __shared__ uint32_t job[4];
+  __shared__ uint32_t job[3];
   LogCell* lt;
   uint64_t* keys;
   ChainEntry* q;
@@ -894,7 +898,7 @@ __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
   const uint32_t num_big = A.meta[0], vbig = A.meta[1], total = A.meta[2];
   for (;;) {
     if (threadIdx.x == 0) {
-      const uint32_t v = atomicAdd(A.counter, 1u);
+      const uint32_t v = atomicAdd(&A.counter[0], 1u);
       job[0] = v;
       if (v < vbig) {  // chunk of a split set: find b with prefix[b] <= v < prefix[b+1]
         uint32_t lo = 0, hi = num_big;
@@ -905,17 +909,40 @@ __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
         }
         job[1] = lo;
         job[2] = v - A.big_prefix[lo];
-        job[3] = A.big_prefix[lo + 1] - A.big_prefix[lo];
       } else if (v < total) {
         job[1] = num_big + (v - vbig);
       }
     }
     __syncthreads();
-    const uint32_t v = job[0], j1 = job[1], j2 = job[2], j3 = job[3];
+    const uint32_t v = job[0], j1 = job[1], j2 = job[2];
     __syncthreads();
     if (v >= total) break;
-    if (v < vbig) process_chunk<V, NW>(A, A.order[j1], j1, j2, j3, keys, q, qcap, fy, lt, sm);
+    if (v < vbig) process_chunk<V, NW>(A, A.order[j1], j1, j2, keys, q, qcap, fy, lt, sm);
     else process_set<V, NW>(A, A.order[j1], keys, q, qcap, fy, lt, sm);
+  }
+}
+
+// Persistent grid over the split sets (order[0 .. meta[0])), after the
+// chunk kernel.
+template <int V, int NW>
+__global__ __launch_bounds__(NW * 64) void k_big_finish(HashArgs A) {
+  __shared__ Shared sm;
+  __shared__ uint32_t job;
+  LogCell* lt;
+  uint64_t* keys;
+  ChainEntry* q;
+  uint32_t qcap;
+  uint16_t* fy;
+  const uint32_t num_big = A.meta[0];
+  if (num_big == 0) return;
+  carve<V, NW>(A, lt, keys, q, qcap, fy);
+  for (;;) {
+    if (threadIdx.x == 0) job = atomicAdd(&A.counter[1], 1u);
+    __syncthreads();
+    const uint32_t b = job;
+    __syncthreads();
+    if (b >= num_big) break;
+    finish_set<V, NW>(A, A.order[b], b, keys, q, qcap, fy, lt, sm);
   }
 }
 
@@ -966,7 +993,8 @@ __global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t nu
       for (uint32_t c = split_log2 + 1; c <= 21; ++c) nb += cnt[c];
     meta[0] = nb;
     num_big_s = nb;
-    *counter = 0;
+    counter[0] = 0;
+    counter[1] = 0;
     carry = 0;
     if (cnt[23]) atomicOr(status, kStatusSetTooLarge);
   }
@@ -987,8 +1015,7 @@ __global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t nu
       const uint32_t s = order[b];
       const uint64_t n = off[s + 1] - off[s];
       c = (uint32_t)((n + (1ull << csize_log2) - 1) >> csize_log2);
-      big_state[2 * (uint64_t)b] = 0;                        // chunks done
-      big_state[2 * (uint64_t)b + 1] = 0x7FF0000000000000ull;  // smallest threshold (+inf)
+      big_state[b] = 0x7FF0000000000000ull;  // smallest chunk threshold (+inf)
     }
     scan[tid] = c;
     __syncthreads();
@@ -1177,6 +1204,11 @@ static hipError_t launch_hash_t(const HashArgs& a, int grid, size_t lds, hipStre
   return hipGetLastError();
 }
 template <int V, int NW>
+static hipError_t launch_finish_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_big_finish<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
+  return hipGetLastError();
+}
+template <int V, int NW>
 static hipError_t launch_one_t(const HashArgs& a, uint64_t set, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((k_hash_one<V, NW>), dim3(1), dim3(NW * 64), lds, s, a, set);
   return hipGetLastError();
@@ -1205,6 +1237,9 @@ static hipError_t occ_t(size_t lds, int* out) {
 
 hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size_t lds, hipStream_t s) {
   PMH_DISPATCH(launch_hash_t, a, grid, lds, s)
+}
+hipError_t launch_big_finish(int variant, const HashArgs& a, int waves, int grid, size_t lds, hipStream_t s) {
+  PMH_DISPATCH(launch_finish_t, a, grid, lds, s)
 }
 hipError_t launch_hash_one(int variant, const HashArgs& a, uint64_t set, int waves, size_t lds, hipStream_t s) {
   PMH_DISPATCH(launch_one_t, a, set, lds, s)

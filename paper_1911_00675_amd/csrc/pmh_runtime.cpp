@@ -68,7 +68,7 @@ int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets) {
   if (hipMalloc(&wb->order, cap * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&wb->small, 8 * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&wb->big_prefix, (cap + 1) * sizeof(uint32_t)) != hipSuccess ||
-      hipMalloc(&wb->big_state, 2 * cap * sizeof(uint64_t)) != hipSuccess) {
+      hipMalloc(&wb->big_state, cap * sizeof(uint64_t)) != hipSuccess) {
     free_work(wb);
     return PMH_ERR_OOM;
   }
@@ -134,6 +134,10 @@ int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, i
   if (launch_order(a.off, a.num_sets, a.split_log2, wa, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (a.split_log2 && launch_big_init(wa, a.m, a.big_keys, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (launch_hash(c->variant, a, waves, (int)grid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (a.split_log2) {
+    const uint64_t fgrid = std::min<uint64_t>((uint64_t)c->num_cu * (uint64_t)per_cu, a.num_sets);
+    if (launch_big_finish(c->variant, a, waves, (int)fgrid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
+  }
   return PMH_OK;
 }
 

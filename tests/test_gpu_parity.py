@@ -218,7 +218,8 @@ def test_schedule_invariance(pmh, variant):
     configs = [dict(), dict(c0=-6.0, grow=1.3, max_rounds=12), dict(max_rounds=1), dict(chain_expect=0.0),
                dict(chain_expect=1e9, mini_expect=1e9, lane_budget=1000000), dict(lane_budget=1),
                dict(mini_expect=0.0), dict(mini_expect=0.0, chain_expect=1e9), dict(waves=1), dict(waves=2),
-               dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0)]
+               dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0),
+               dict(kmax_refresh=3, max_rounds=1)]
     for cfg in configs:
         ctx.set_tuning(**cfg)
         sig, st = _keys(ctx, b)
