@@ -40,6 +40,41 @@ def harmonic(n):
     return float(np.sum(1.0 / np.arange(1, n + 1)))
 
 
+KERNEL_SOURCES = ("paper_1911_00675_amd/csrc/pmh_kernels.hip", "paper_1911_00675_amd/csrc/pmh_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hash_persistent_mixed_sizes_m1024_traffic.json")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(variant, num_sets):
+    """HBM bytes per launch of the hash kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the counters' reading for a copy
+    of known size; None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None, "no committed counter summary"
+    if t.get("kernel_source_sha256") != kernel_source_sha():
+        return None, "kernel changed since the counters were taken"
+    if t.get("num_sets") != num_sets:
+        return None, "counters were taken on another workload size"
+    k = t["kernels"].get(f"pmh{variant}")
+    if k is None:
+        return None, "no counters for this variant"
+    cal = t["calibration"]
+    return (k["fetch_kib"] * 1024.0 * cal["fetch_factor"] + k["write_kib"] * 1024.0 * cal["write_factor"],
+            f"rocprofv3 FETCH_SIZE x {cal['fetch_factor']:.3f} + WRITE_SIZE x {cal['write_factor']:.3f} "
+            f"(copy calibration), {os.path.relpath(TRAFFIC_FILE, ROOT)}")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,16 +133,19 @@ def main():
         assert ctxs[v].status() == pmh.PMH_OK
     ev = [{v: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for v in VARIANTS}
           for _ in range(args.steps)]
+    for v in VARIANTS:  # HIP events around the persistent hash kernel itself, on the launch stream
+        ctxs[v].timing_begin(args.steps)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    launch_ms = {v: float(np.mean([e[v][0].elapsed_time(e[v][1]) for e in ev])) for v in VARIANTS}
+    call_ms = {v: float(np.mean([e[v][0].elapsed_time(e[v][1]) for e in ev])) for v in VARIANTS}
+    launch_ms = {v: float(np.mean(ctxs[v].timing_read(args.steps))) for v in VARIANTS}
     ms_per_step = elapsed * 1e3 / args.steps
     value = len(VARIANTS) * N / (elapsed / args.steps)
-    log(f"batched: {ms_per_step:.3f} ms/step, per launch {launch_ms}")
+    log(f"batched: {ms_per_step:.3f} ms/step, per call {call_ms}, hash kernel {launch_ms}")
     if args.copy_calibrate:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -128,10 +166,12 @@ def main():
         roof[v] = ops / (launch_ms[v] * 1e-3)
     dom = max(VARIANTS, key=lambda v: launch_ms[v])
     hbm_bytes = 16.0 * N + 8.0 * (S + 1) + 20.0 * S * M
+    traffic, traffic_note = measured_traffic(dom, S)
     roofline = {
         "bound": "alu", "kernel": f"k_hash_persistent<ProbMinHash{dom}>",
         "achieved": roof[dom] / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
-        "frac": roof[dom] / PEAK_VALU, "traffic": None,
+        "frac": roof[dom] / PEAK_VALU, "traffic": traffic, "traffic_note": traffic_note,
+        "launch_ms": launch_ms[dom], "timing": "HIP events around the persistent kernel on its stream",
         "ops_model": {"per_element": OPS_PER_ELEMENT[dom], "per_point": OPS_PER_POINT[dom],
                       "elements": units_e, "points": units_p},
         "per_variant_frac": {f"pmh{v}": roof[v] / PEAK_VALU for v in VARIANTS},
@@ -199,6 +239,7 @@ def main():
                                f"Pareto(1.5) weights, m={M}, ProbMinHash1+ProbMinHash3, batched persistent",
                    "num_sets": S, "num_elements": N, "m": M, "variants": list(VARIANTS),
                    "per_launch_ms": {f"pmh{v}": launch_ms[v] for v in VARIANTS},
+                   "per_call_ms": {f"pmh{v}": call_ms[v] for v in VARIANTS},
                    "elements_per_s": {f"pmh{v}": N / (launch_ms[v] * 1e-3) for v in VARIANTS},
                    "components_per_s": {f"pmh{v}": S * M / (launch_ms[v] * 1e-3) for v in VARIANTS}},
         "roofline": roofline,

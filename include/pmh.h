@@ -122,6 +122,15 @@ int pmh_hash_sets_graph(pmh_ctx* ctx, const uint64_t* ids, const double* weights
                         const uint64_t* offsets, uint64_t num_sets, uint32_t* out_idx,
                         double* out_val, uint64_t* out_id, uint64_t* out_keys, void* stream);
 
+/* Kernel timing for benchmarks.  After pmh_timing_begin(ctx, n) the next n
+ * pmh_hash_sets calls record a HIP event pair right around their persistent
+ * hash kernel, on the call's stream (the ordering and split-set kernels stay
+ * outside).  pmh_timing_read waits for the n pairs and writes their durations
+ * in milliseconds to [host] ms[0..n); PMH_ERR_NOT_READY if fewer than n calls
+ * were recorded.  The events are owned by the context. */
+int pmh_timing_begin(pmh_ctx* ctx, int n);
+int pmh_timing_read(pmh_ctx* ctx, float* ms, int n);
+
 /* Synchronize `stream`, then return and clear the context's sticky kernel
  * errors (PMH_ERR_WEIGHT, PMH_ERR_SET_TOO_LARGE) or PMH_OK. */
 int pmh_get_status(pmh_ctx* ctx, void* stream);

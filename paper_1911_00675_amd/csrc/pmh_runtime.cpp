@@ -119,7 +119,8 @@ HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const
   return a;
 }
 
-int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, int per_cu, int waves) {
+int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, int per_cu, int waves,
+                    hipEvent_t ev0, hipEvent_t ev1) {
   if (a.num_sets == 0) return PMH_OK;
   if (waves <= 0) waves = effective_waves(c);
   const size_t lds = lds_bytes(c->variant, c->m, waves);
@@ -133,7 +134,9 @@ int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, i
   const WorkArgs wa = wb->args();
   if (launch_order(a.off, a.num_sets, a.split_log2, wa, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (a.split_log2 && launch_big_init(wa, a.m, a.big_keys, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (launch_hash(c->variant, a, waves, (int)grid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (a.split_log2) {
     const uint64_t fgrid = std::min<uint64_t>((uint64_t)c->num_cu * (uint64_t)per_cu, a.num_sets);
     if (launch_big_finish(c->variant, a, waves, (int)fgrid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
@@ -239,6 +242,7 @@ void pmh_destroy(pmh_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   free_work(&c->work);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->table_mem) (void)hipFree(c->table_mem);
   if (c->status) (void)hipFree(c->status);
   if (c->stats) (void)hipFree(c->stats);
@@ -263,7 +267,41 @@ int pmh_hash_sets(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64
   rc = ensure_work(c, &c->work, num_sets);
   if (rc) return rc;
   HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
-  return enqueue_batched(c, a, &c->work, (hipStream_t)stream);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->tnext < c->tcount) {
+    ev0 = c->tev[2 * c->tnext];
+    ev1 = c->tev[2 * c->tnext + 1];
+    c->tnext++;
+  }
+  return enqueue_batched(c, a, &c->work, (hipStream_t)stream, 0, 0, ev0, ev1);
+}
+
+int pmh_timing_begin(pmh_ctx* c, int n) {
+  if (!c || n < 0 || n > 1 << 16) return PMH_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  while ((int)c->tev.size() < 2 * n) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return PMH_ERR_DEVICE;
+    c->tev.push_back(e);
+  }
+  c->tnext = 0;
+  c->tcount = n;
+  return PMH_OK;
+}
+
+int pmh_timing_read(pmh_ctx* c, float* ms, int n) {
+  if (!c || !ms || n < 0) return PMH_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  if (n > c->tnext) return PMH_ERR_NOT_READY;
+  for (int k = 0; k < n; ++k) {
+    if (hipEventSynchronize(c->tev[2 * k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms[k], c->tev[2 * k], c->tev[2 * k + 1]) != hipSuccess)
+      return PMH_ERR_DEVICE;
+  }
+  c->tcount = 0;
+  return PMH_OK;
 }
 
 int pmh_hash_sets_plain(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off,

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <vector>
 
 #include "pmh_internal.h"
 
@@ -71,6 +72,8 @@ struct pmh_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   pmh::GraphKey gkey{};
+  std::vector<hipEvent_t> tev;  // kernel timing: event pairs (start, stop) per recorded call
+  int tnext = 0, tcount = 0;
   std::mutex mu;
 };
 
@@ -80,6 +83,8 @@ int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets);
 HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
                    uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, const WorkBuf* wb);
 // Order kernel, split-set init and the persistent grid (per_cu workgroups per
-// CU and waves per workgroup from the tuning when 0).
-int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, int per_cu = 0, int waves = 0);
+// CU and waves per workgroup from the tuning when 0); ev0/ev1, when given, are
+// recorded right before and after the persistent hash kernel.
+int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, int per_cu = 0, int waves = 0,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 }  // namespace pmh

@@ -35,6 +35,8 @@ SIGNATURES = {
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_graph": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_get_status": (_i32, [_vp, _vp]),
+    "pmh_timing_begin": (_i32, [_vp, _i32]),
+    "pmh_timing_read": (_i32, [_vp, _vp, _i32]),
     "pmh_set_tuning": (_i32, [_vp, _vp]),
     "pmh_get_tuning": (_i32, [_vp, _vp]),
     "pmh_autotune": (_i32, [_vp] * 4 + [_u64, _i32, _vp, _vp]),
@@ -181,6 +183,16 @@ class Context:
     def status(self, stream=None) -> int:
         """Synchronize and return (then clear) sticky kernel errors."""
         return lib().pmh_get_status(self._c, _stream_ptr(stream))
+
+    # ------------------------------------------------------------------ timing
+    def timing_begin(self, n: int):
+        """Record the persistent kernel's duration in the next n batched calls."""
+        _check(lib().pmh_timing_begin(self._c, int(n)), "pmh_timing_begin")
+
+    def timing_read(self, n: int) -> np.ndarray:
+        out = np.zeros(n, dtype=np.float32)
+        _check(lib().pmh_timing_read(self._c, out.ctypes.data_as(ctypes.c_void_p), int(n)), "pmh_timing_read")
+        return out
 
     # ------------------------------------------------------------------ tuning
     def get_tuning(self) -> pmh_tuning:
