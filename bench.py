@@ -26,12 +26,14 @@ sys.path.insert(0, ROOT)
 M = 1024
 SEED = 0x5EED
 VARIANTS = (1, 3)
-# VALU lane-instructions per algorithmic unit on gfx950, counted in the ISA of
-# this library's primitives ("Roofline"): an element needs its
-# weight inverse, its key hash and its first point; a point below the final
-# stop limit needs its value, its label and one LDS min.
-OPS_PER_ELEMENT = {1: 117, 3: 68}
-OPS_PER_POINT = {1: 112, 3: 63}
+# VALU instructions per algorithmic unit on gfx950, counted on the common path
+# of this library's own primitives in their compiled ISA: an element needs its
+# weight check, 1/w, key hash (32) and its first point; a point below the final
+# stop limit needs its word hash, value, key, label and one LDS min
+# (ProbMinHash1 83 with the Exp(1) logarithm, ProbMinHash3 45 with the
+# truncated-exponential fast path).
+OPS_PER_ELEMENT = {1: 32 + 83, 3: 32 + 45}
+OPS_PER_POINT = {1: 83, 3: 45}
 PEAK_VALU = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_HBM = 8.0e12                     # bytes/s
 
@@ -173,7 +175,8 @@ def main():
         "frac": roof[dom] / PEAK_VALU, "traffic": traffic, "traffic_note": traffic_note,
         "launch_ms": launch_ms[dom], "timing": "HIP events around the persistent kernel on its stream",
         "ops_model": {"per_element": OPS_PER_ELEMENT[dom], "per_point": OPS_PER_POINT[dom],
-                      "elements": units_e, "points": units_p},
+                      "elements": units_e, "points": units_p,
+                      "points_rule": "m*H_m per non-empty set (points below the final stop limit)"},
         "per_variant_frac": {f"pmh{v}": roof[v] / PEAK_VALU for v in VARIANTS},
         "hbm_algorithmic_GBps": hbm_bytes / (launch_ms[dom] * 1e-3) / 1e9,
         "hbm_frac": hbm_bytes / (launch_ms[dom] * 1e-3) / PEAK_HBM,
