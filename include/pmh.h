@@ -202,8 +202,11 @@ int pmh_server_fetch(pmh_server* s, uint64_t ticket, uint32_t* idx, double* val,
 /* Open-loop replay: submits request r at arrival[r] seconds after the start
  * (busy-waiting for the scheduled time), then waits for all results.
  * latency[r] (host, seconds) = completion time - scheduled arrival.  Requests
- * are given in CSR form on the host; signatures are written to [host]
- * out_idx/out_id ([num][m], may be NULL).  *wall receives the elapsed time. */
+ * are given in CSR form on the host; before the clock starts they are staged
+ * once in pinned host memory (owned by the call, freed on return), from which
+ * each batch is copied to the device directly.  Signatures are written to
+ * [host] out_idx/out_id ([num][m], may be NULL).  *wall receives the elapsed
+ * time. */
 int pmh_server_replay(pmh_server* s, const uint64_t* ids, const double* weights, const uint64_t* offsets,
                       uint64_t num, const double* arrival, double* latency, uint32_t* out_idx,
                       uint64_t* out_id, double* wall);

