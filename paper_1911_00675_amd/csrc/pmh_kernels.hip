@@ -710,7 +710,37 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
   }
   __syncthreads();
   const uint32_t batch = kEpt * BS;
+  // The weights and ids of the next batch are loaded while this one runs
+  // (not for ProbMinHash3, where the extra registers cost a workgroup per CU
+  // at m = 1024 and the loads are better issued on demand).
+  constexpr bool kPrefetch = V != 3;
+  double wn[kEpt];
+  uint64_t idn[kEpt];
+#pragma unroll
+  for (uint32_t k = 0; k < kEpt; ++k) {
+    const uint32_t p = p0 + k * BS + tid;
+    wn[k] = kPrefetch && p < p1 ? R.w[p] : 0.0;
+    idn[k] = kPrefetch && p < p1 ? R.ids[p] : 0;
+  }
   for (uint32_t base = p0, nb = 0; base < p1; base += batch, ++nb) {
+    double wc[kEpt];
+    uint64_t idc[kEpt];
+#pragma unroll
+    for (uint32_t k = 0; k < kEpt; ++k) {
+      if constexpr (kPrefetch) {
+        wc[k] = wn[k];
+        idc[k] = idn[k];
+        const uint32_t p = base + batch + k * BS + tid;
+        if (p < p1) {
+          wn[k] = R.w[p];
+          idn[k] = R.ids[p];
+        }
+      } else {
+        const uint32_t p = base + k * BS + tid;
+        wc[k] = p < p1 ? R.w[p] : 0.0;
+        idc[k] = 0;
+      }
+    }
     const uint64_t kmax = shared_kmax(sm);
     // points above the stop limit's value are never generated: the expected
     // count of an element is its weight times the smaller of T and that value
@@ -720,7 +750,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
     for (uint32_t k = 0; k < kEpt; ++k) {
       const uint32_t p = base + k * BS + tid;
       if (p >= p1) break;
-      const double w = R.w[p];
+      const double w = wc[k];
       if (!weight_ok(w)) continue;
       PMH_STAT(sm, kStElems, 1);
       const double lam = w * Teff;  // expected points generated
@@ -733,7 +763,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
         continue;
       }
       const double winv = 1.0 / w;
-      const uint64_t K = mix64(R.ids[p] ^ R.K0);
+      const uint64_t K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
       const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
 #ifdef PMH_STATS
       // wave-level cost of this element slot: the longest lane
