@@ -172,7 +172,9 @@ int pmh_get_table(pmh_ctx* ctx, int which, double* out, uint32_t count);
  * arrays (for validation): what 0 log(in), 1 log1p(in), 2 expm1(in),
  * 3 Exp(1) from word in_u, 4 mix64(in_u), 5 truncated exponential of element
  * key in_u[k] at point k+1 (PMH3 constants), 6 Lemire(m) label of that point,
- * 7 ProbMinHash1 fixed-point spacing of that point, 8 stream logarithm(in). */
+ * 7 ProbMinHash1 fixed-point spacing of that point, 8 stream logarithm(in),
+ * 9 inclusive prefix sum of in_u over each aligned group of 64 entries (the
+ * chain-mode spacing scan; entries < 2^51), 10 the same over groups of 8. */
 int pmh_debug_eval(pmh_ctx* ctx, int what, const double* in, const uint64_t* in_u, double* out,
                    uint64_t* out_u, uint64_t n, void* stream);
 

@@ -45,11 +45,18 @@ constexpr uint32_t kEpt = 2;                     // elements per thread per batc
 // LDS per workgroup and added to HashArgs::points[0..15] when a set ends.
 #ifdef PMH_STATS
 #define PMH_STAT(sm, i, v) atomicAdd(&(sm).st[i], (uint32_t)(v))
+// shader-clock cycles of a phase, summed over waves (lane 0 of each wave)
+#define PMH_TIC(t) const uint64_t t = clock64()
+#define PMH_TOC(sm, i, t) \
+  if ((threadIdx.x & 63) == 0) atomicAdd(&(sm).st[i], (uint32_t)(clock64() - (t)))
 #else
 #define PMH_STAT(sm, i, v) ((void)0)
+#define PMH_TIC(t) ((void)0)
+#define PMH_TOC(sm, i, t) ((void)0)
 #endif
 enum { kStSets, kStRounds, kStElems, kStLanePts, kStLaneIters, kStLaneApply, kStMiniSteps, kStMiniPts,
-       kStMiniElems, kStChainTiles, kStChainPts, kStChainElems, kStFlush, kStBlockMax, kStApply, kStRepairs, kStCount };
+       kStMiniElems, kStChainTiles, kStChainPts, kStChainElems, kStFlush, kStBlockMax, kStApply, kStRepairs,
+       kStCycBatch, kStCycBarrier, kStCycChain, kStCycMini, kStCycBlockMax, kStCycSet, kStCount };
 
 // ---------------------------------------------------------------- randomness
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -204,11 +211,6 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
   uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
   return ((uint64_t)hi << 32) | lo;
 }
-__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
-  uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d);
-  uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d);
-  return ((uint64_t)hi << 32) | lo;
-}
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   for (int d = 32; d >= 1; d >>= 1) {
     uint64_t o = shfl_xor_u64(v, d);
@@ -220,12 +222,53 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
   return v;
 }
+// DPP lane moves (gfx9 row operations).  update_dpp(old = 0, ...) writes 0
+// where the source lane is outside the row or the row is masked off.
+constexpr int kDppRowShr = 0x110;     // + n: lane i takes lane i - n of its row of 16
+constexpr int kDppRowBcast15 = 0x142; // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143; // lane 31 to rows 2 and 3
+template <int N>
+__device__ __forceinline__ uint32_t dpp_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowShr + N, 0xf, 0xf, true);
+}
+// Inclusive prefix sum over the 64 lanes of u32 values whose total fits 32 bits.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+  x += dpp_shr<1>(x);
+  x += dpp_shr<2>(x);
+  x += dpp_shr<4>(x);
+  x += dpp_shr<8>(x);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast15, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppRowBcast31, 0xc, 0xf, false);
+  return x;
+}
+// Inclusive prefix sum over the 64 lanes of fixed-point spacings v < 2^51:
+// scanned as 26-bit low and 25-bit high limbs (64 of each fit 32 bits) with
+// DPP row moves instead of LDS-crossbar shuffles.
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane) {
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t o = shfl_up_u64(v, d);
-    if (lane >= d) v += o;
-  }
-  return v;
+  (void)lane;
+  const uint32_t lo = wave_incl_scan_u32((uint32_t)v & 0x3FFFFFFu);
+  const uint32_t hi = wave_incl_scan_u32((uint32_t)(v >> 26));
+  return ((uint64_t)hi << 26) + lo;
+}
+// The same within aligned groups of 8 lanes (j = lane & 7).
+__device__ __forceinline__ uint32_t group8_incl_scan_u32(uint32_t x, int j) {
+  uint32_t o = dpp_shr<1>(x);
+  x += j >= 1 ? o : 0u;
+  o = dpp_shr<2>(x);
+  x += j >= 2 ? o : 0u;
+  o = dpp_shr<4>(x);
+  x += j >= 4 ? o : 0u;
+  return x;
+}
+__device__ __forceinline__ uint64_t group8_incl_scan_u64(uint64_t v, int j) {
+  const uint32_t lo = group8_incl_scan_u32((uint32_t)v & 0x3FFFFFFu, j);
+  const uint32_t hi = group8_incl_scan_u32((uint32_t)(v >> 26), j);
+  return ((uint64_t)hi << 26) + lo;
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
 }
 __device__ __forceinline__ uint64_t lds_load_u64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -249,7 +292,7 @@ struct Shared {
   uint32_t mhead, mtail;  // mini-chain queue: back of the queue array
   uint32_t item;
 #ifdef PMH_STATS
-  uint32_t st[16];
+  uint32_t st[24];
 #endif
 };
 
@@ -271,6 +314,7 @@ __device__ __forceinline__ uint64_t shared_kmax(Shared& sm) {
 template <int NW>
 __device__ uint64_t block_max_keys(const uint64_t* keys, uint32_t m, Shared& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  PMH_TIC(t_bm);
   uint64_t v = 0;
   for (uint32_t k = tid; k < m; k += NW * 64) {
     uint64_t x = keys[k];
@@ -286,6 +330,7 @@ __device__ uint64_t block_max_keys(const uint64_t* keys, uint32_t m, Shared& sm)
     sm.kmax = r;
   }
   __syncthreads();
+  PMH_TOC(sm, kStCycBlockMax, t_bm);
   return sm.kmax;
 }
 
@@ -526,7 +571,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       lds_min(keys, label, key);
     }
     if (first < 64) break;
-    if constexpr (V == 1 || V == 2) tacc = shfl_u64(tl, 63);
+    if constexpr (V == 1 || V == 2) tacc = readlane_u64(tl, 63);
     i0 += 64;
     if ((tile & 15) == 0) {  // tighten the shared stop limit now and then
       const uint64_t km = wave_max_keys(keys, m, lane);
@@ -578,11 +623,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
     uint64_t key = kEmptyKey, tl = 0;
     bool stop;
     if constexpr (V == 1) {
-      uint64_t d = valid ? (uint64_t)(exp1(w0, lt) * 0x1p32) : 0;
-      for (int dd = 1; dd < 8; dd <<= 1) {
-        const uint64_t o = shfl_u64(d, lane - dd >= leader ? lane - dd : lane);
-        if (j >= dd) d += o;
-      }
+      const uint64_t d = group8_incl_scan_u64(valid ? (uint64_t)(exp1(w0, lt) * 0x1p32) : 0, j);
       tl = tacc + d;
       x = winv * ((double)tl * 0x1p-32);
       key = make_key(x, p);
@@ -628,6 +669,7 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint16_t* g = (V == 2 || V == 4) ? fy + (size_t)wv * R.m : nullptr;
   const uint32_t qtail = sm.qtail;
+  PMH_TIC(t_chain);
   for (;;) {  // long streams first
     uint32_t e = 0;
     if (lane == 0) e = atomicAdd(&sm.qhead, 1u);
@@ -636,13 +678,18 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
     const ChainEntry ce = q[e];
     chain_elem<V>(A, R, ce, 1.0 / R.w[ce.p], mix64(R.ids[ce.p] ^ R.K0), keys, g, sm);
   }
+  PMH_TOC(sm, kStCycChain, t_chain);
+  PMH_TIC(t_mini);
   if constexpr (V == 1 || V == 3) mini_pass<V>(A, R, keys, q, sm);
+  PMH_TOC(sm, kStCycMini, t_mini);
+  PMH_TIC(t_bar);
   __syncthreads();
   if (threadIdx.x == 0) {
     sm.qhead = sm.qtail = 0;
     sm.mhead = sm.mtail = 0;
   }
   __syncthreads();
+  PMH_TOC(sm, kStCycBarrier, t_bar);
 }
 
 // ------------------------------------------------------------- one set
@@ -665,7 +712,7 @@ __device__ __forceinline__ Round set_round(const HashArgs& A, uint64_t set, uint
   R.T = R.Tprev = 0.0;
   if (n64 > kMaxSet && tid == 0) atomicOr(A.status, kStatusSetTooLarge);
 #ifdef PMH_STATS
-  if (tid < 16) sm.st[tid] = 0;
+  if (tid < 24) sm.st[tid] = 0;
   __syncthreads();
   if (tid == 0) PMH_STAT(sm, kStSets, 1);
 #endif
@@ -741,6 +788,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
         idc[k] = 0;
       }
     }
+    PMH_TIC(t_batch);
     const uint64_t kmax = shared_kmax(sm);
     // points above the stop limit's value are never generated: the expected
     // count of an element is its weight times the smaller of T and that value
@@ -774,9 +822,12 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
       (void)steps;
 #endif
     }
+    PMH_TOC(sm, kStCycBatch, t_batch);
+    PMH_TIC(t_bar);
     __syncthreads();
     const uint32_t qt = sm.qtail + sm.mtail;  // read by every thread before anyone pushes again
     __syncthreads();
+    PMH_TOC(sm, kStCycBarrier, t_bar);
     const bool flush = qt + batch > qcap;
     if (flush && tid == 0) PMH_STAT(sm, kStFlush, 1);
     if (flush) chain_pass<V, NW>(A, R, keys, q, fy, sm);
@@ -833,9 +884,11 @@ template <int V, int NW>
 __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
                             uint16_t* fy, const LogCell* lt, Shared& sm) {
   Round R = set_round<NW>(A, set, qcap, lt, sm);
+  PMH_TIC(t_set);
   for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = kEmptyKey;
   const double W = block_weight_sum<NW>(A, R, 0, R.n, sm);
   if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kEmptyKey, keys, q, fy, sm);
+  PMH_TOC(sm, kStCycSet, t_set);
   epilogue<NW>(A, R, set, keys, sm);
 }
 
@@ -1214,6 +1267,15 @@ __global__ void k_debug(int what, const double* in, const uint64_t* in_u, double
   }
 }
 
+// Wave prefix sums of the fixed-point spacings (64-lane chains: what 9; 8-lane
+// groups: what 10), every lane participating; inputs beyond n count as 0.
+__global__ void k_debug_scan(int what, const uint64_t* in_u, uint64_t* out_u, uint64_t n) {
+  const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  const uint64_t v = k < n ? in_u[k] : 0;
+  const uint64_t r = what == 9 ? wave_incl_scan_u64(v, threadIdx.x & 63) : group8_incl_scan_u64(v, threadIdx.x & 7);
+  if (k < n) out_u[k] = r;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1314,6 +1376,10 @@ hipError_t launch_debug_eval(int what, const double* in, const uint64_t* in_u, d
                              uint64_t n, uint32_t m, int variant, Tables t, hipStream_t s) {
   (void)variant;
   if (n == 0) return hipSuccess;
+  if (what == 9 || what == 10) {
+    hipLaunchKernelGGL(k_debug_scan, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, what, in_u, out_u, n);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_debug, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, what, in, in_u, out, out_u, n,
                      m, t);
   return hipGetLastError();

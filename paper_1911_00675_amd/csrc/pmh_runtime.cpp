@@ -220,8 +220,8 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   if (!rc && hipMalloc(&c->status, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_OOM;
   if (!rc && hipMemset(c->status, 0, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
 #ifdef PMH_STATS
-  if (!rc && hipMalloc(&c->stats, 16 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_OOM;
-  if (!rc && hipMemset(c->stats, 0, 16 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (!rc && hipMalloc(&c->stats, 24 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_OOM;
+  if (!rc && hipMemset(c->stats, 0, 24 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
 #endif
   if (!rc && launch_init_tables(variant, m, c->t, nullptr) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = PMH_ERR_DEVICE;
@@ -455,9 +455,9 @@ int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
 
 int pmh_debug_eval(pmh_ctx* c, int what, const double* in, const uint64_t* in_u, double* out, uint64_t* out_u,
                    uint64_t n, void* stream) {
-  if (!c || what < 0 || what > 8) return PMH_ERR_ARG;
-  const bool uses_u = what >= 3 && what <= 7;
-  const bool out_is_u = what == 4 || what == 6 || what == 7;
+  if (!c || what < 0 || what > 10) return PMH_ERR_ARG;
+  const bool uses_u = (what >= 3 && what <= 7) || what >= 9;
+  const bool out_is_u = what == 4 || what == 6 || what == 7 || what >= 9;
   if ((uses_u && !in_u) || (!uses_u && !in) || (out_is_u && !out_u) || (!out_is_u && !out)) return PMH_ERR_ARG;
   if (what == 5 && c->variant != 3) return PMH_ERR_ARG;
   DeviceGuard g(c->device);
@@ -468,13 +468,13 @@ int pmh_debug_eval(pmh_ctx* c, int what, const double* in, const uint64_t* in_u,
 
 #ifdef PMH_STATS
 // Statistics build only (not part of the product ABI): read and optionally
-// reset the 16 event counters accumulated by the kernels.
-int pmh_stats_read(pmh_ctx* c, uint64_t* out16, int reset) {
-  if (!c || !out16 || !c->stats) return PMH_ERR_ARG;
+// reset the 24 event and cycle counters accumulated by the kernels.
+int pmh_stats_read(pmh_ctx* c, uint64_t* out24, int reset) {
+  if (!c || !out24 || !c->stats) return PMH_ERR_ARG;
   DeviceGuard g(c->device);
   if (hipDeviceSynchronize() != hipSuccess) return PMH_ERR_DEVICE;
-  if (hipMemcpy(out16, c->stats, 16 * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return PMH_ERR_DEVICE;
-  if (reset && hipMemset(c->stats, 0, 16 * sizeof(uint64_t)) != hipSuccess) return PMH_ERR_DEVICE;
+  if (hipMemcpy(out24, c->stats, 24 * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return PMH_ERR_DEVICE;
+  if (reset && hipMemset(c->stats, 0, 24 * sizeof(uint64_t)) != hipSuccess) return PMH_ERR_DEVICE;
   return PMH_OK;
 }
 #endif

@@ -74,6 +74,16 @@ def test_primitives_bitwise(pmh):
     assert np.array_equal(ctx.debug_eval(8, xs).view(np.uint64),
                           np.array([O.stream_log(v) for v in xs]).view(np.uint64))
     assert np.array_equal(ctx.table(9, 512).view(np.uint64), O.stream_log_table().view(np.uint64))
+    # wave prefix sums of fixed-point spacings (chains: 64 lanes, mini-chains: 8)
+    sp_in = rng.integers(0, 2**51, size=64 * 300, dtype=np.uint64)
+    sp_in[:64] = np.uint64(2**51 - 1)  # largest spacings
+    sp_in[64:128] = 0
+    for what, g in ((9, 64), (10, 8)):
+        want = np.cumsum(sp_in.reshape(-1, g), axis=1, dtype=np.uint64).reshape(-1)
+        assert np.array_equal(ctx.debug_eval(what, sp_in), want), what
+        tail = sp_in[:100]  # a partial last group: missing entries count as 0
+        assert np.array_equal(ctx.debug_eval(what, tail),
+                              np.concatenate([np.cumsum(tail[i:i + g], dtype=np.uint64) for i in range(0, 100, g)]))
     sp = ctx.debug_eval(7, Ks)
     want = np.array([int(O.exp1_of_word(O.word(int(K), k + 1, 0)) * 2.0 ** 32) for k, K in enumerate(Ks)],
                     dtype=np.uint64)
