@@ -83,7 +83,7 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
           break;
         case 2:
           for (double ce : {16.0, 32.0, 48.0, 96.0, 192.0}) add([&](Tuning& t) { t.chain_expect = ce; });
-          for (double me : {1.0, 2.0, 3.0, 5.0, 8.0}) add([&](Tuning& t) { t.mini_expect = me; });
+          for (double me : {3.0, 12.0, 24.0, 48.0, 96.0}) add([&](Tuning& t) { t.mini_expect = me; });
           break;
         case 3:
           for (int lb : {2, 4, 8, 16}) add([&](Tuning& t) { t.lane_budget = lb; });
