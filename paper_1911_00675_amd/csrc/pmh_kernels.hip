@@ -74,7 +74,19 @@ __device__ __forceinline__ uint64_t pbase(uint64_t K, uint32_t i) {
 }
 __device__ __forceinline__ uint64_t word(uint64_t pb, uint32_t t) { return mix64(pb + (uint64_t)t * kPhi); }
 __device__ __forceinline__ double u32v(uint64_t w) { return (double)(uint32_t)(w >> 32) * 0x1p-32; }
-__device__ __forceinline__ double upos32(uint64_t w) { return (double)((w >> 32) + 1) * 0x1p-32; }
+// ((w >> 32) + 1) 2^-32, exact (the sum is at most 2^32)
+__device__ __forceinline__ double upos32(uint64_t w) { return ((double)(uint32_t)(w >> 32) + 1.0) * 0x1p-32; }
+// floor(s 2^32) of a spacing 0 <= s < 2^20, exact: the integral value t < 2^52
+// is the low 52 bits of t + 2^52
+__device__ __forceinline__ uint64_t spacing_fixed(double s) {
+  const double t = trunc(s * 0x1p32);
+  return (uint64_t)__double_as_longlong(t + 0x1p52) & 0xFFFFFFFFFFFFFull;
+}
+// T 2^-32 of the fixed-point accumulator, rounded once (exact below 2^52)
+__device__ __forceinline__ double fixed_value(uint64_t T) {
+  if (T < (1ull << 52)) return (__longlong_as_double((long long)(T | 0x4330000000000000ull)) - 0x1p52) * 0x1p-32;
+  return (double)T * 0x1p-32;
+}
 __device__ __forceinline__ double u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
 
 // ln x = e ln 2 + 2 atanh(s), x = 2^e f, f in [sqrt(1/2), sqrt(2)), s = (f-1)/(f+1).
@@ -374,8 +386,8 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         return step;
       }
       const uint64_t w0 = mix64(pb);
-      tacc += (uint64_t)(exp1(w0, lt) * 0x1p32);
-      const double x = winv * ((double)tacc * 0x1p-32);
+      tacc += spacing_fixed(exp1(w0, lt));
+      const double x = winv * fixed_value(tacc);
       PMH_STAT(sm, kStLanePts, 1);
       if (!(x < R.T)) return step + 1;
       const uint64_t key = make_key(x, p);
@@ -423,8 +435,8 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       const uint64_t w0 = mix64(pb);
       double x;
       if constexpr (V == 2) {
-        tacc += (uint64_t)((t.beta[i] * exp1(w0, lt)) * 0x1p32);
-        x = winv * ((double)tacc * 0x1p-32);
+        tacc += spacing_fixed(t.beta[i] * exp1(w0, lt));
+        x = winv * fixed_value(tacc);
         if (!(x < R.T)) return (int)step + 1;
         if (make_key(x, p) >= kmax) return (int)step + 1;
       } else {
@@ -491,10 +503,10 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       if (valid) {
         double E = exp1(w0, lt);
         if constexpr (V == 2) E = t.beta[i] * E;
-        d = (uint64_t)(E * 0x1p32);
+        d = spacing_fixed(E);
       }
       tl = tacc + wave_incl_scan_u64(d, lane);
-      x = winv * ((double)tl * 0x1p-32);
+      x = winv * fixed_value(tl);
       key = make_key(x, p);
       stop = !valid || !(x < R.T) || key >= kmax;
     } else if constexpr (V == 3) {
@@ -623,9 +635,9 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
     uint64_t key = kEmptyKey, tl = 0;
     bool stop;
     if constexpr (V == 1) {
-      const uint64_t d = group8_incl_scan_u64(valid ? (uint64_t)(exp1(w0, lt) * 0x1p32) : 0, j);
+      const uint64_t d = group8_incl_scan_u64(valid ? spacing_fixed(exp1(w0, lt)) : 0, j);
       tl = tacc + d;
-      x = winv * ((double)tl * 0x1p-32);
+      x = winv * fixed_value(tl);
       key = make_key(x, p);
       stop = !valid || !(x < R.T) || key >= kmax;
     } else {
@@ -1261,7 +1273,7 @@ __global__ void k_debug(int what, const double* in, const uint64_t* in_u, double
       out_u[k] = lemire(mix64(pb), pb, m);
       break;
     }
-    case 7: out_u[k] = (uint64_t)(exp1(mix64(pbase(in_u[k], (uint32_t)k + 1)), (const LogCell*)t.ltab) * 0x1p32); break;
+    case 7: out_u[k] = spacing_fixed(exp1(mix64(pbase(in_u[k], (uint32_t)k + 1)), (const LogCell*)t.ltab)); break;
     case 8: out[k] = stream_log(in[k], (const LogCell*)t.ltab); break;
     default: break;
   }
