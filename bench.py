@@ -27,13 +27,15 @@ M = 1024
 SEED = 0x5EED
 VARIANTS = (1, 3)
 # VALU instructions per algorithmic unit on gfx950, counted on the common path
-# of this library's own primitives in their compiled ISA: an element needs its
-# weight check, 1/w, key hash (32) and its first point; a point below the final
-# stop limit needs its word hash, value, key, label and one LDS min
-# (ProbMinHash1 83 with the Exp(1) logarithm, ProbMinHash3 45 with the
+# of this library's own primitives in their compiled ISA (constants hoisted, the
+# rare branches -- Lemire redraw, truncated-exponential rejection, accumulator
+# above 2^52 -- left out): an element needs its weight check, 1/w and key hash
+# (32) and its first point; a point below the final stop limit needs its word
+# hash, value, key, label and one LDS min (ProbMinHash1 62 with the Exp(1)
+# logarithm and the fixed-point step, ProbMinHash3 33 with the
 # truncated-exponential fast path).
-OPS_PER_ELEMENT = {1: 32 + 83, 3: 32 + 45}
-OPS_PER_POINT = {1: 83, 3: 45}
+OPS_PER_ELEMENT = {1: 32 + 62, 3: 32 + 33}
+OPS_PER_POINT = {1: 62, 3: 33}
 PEAK_VALU = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_HBM = 8.0e12                     # bytes/s
 
