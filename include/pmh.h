@@ -82,7 +82,7 @@ typedef struct {
   int waves;          /* wavefronts per workgroup: 1, 2 or 4 */
   int kmax_refresh;   /* element batches between stop-limit refreshes (>= 1) */
   int blocks_per_cu;  /* persistent grid = CUs * this (0: occupancy limit) */
-  double mini_expect; /* ProbMinHash1/3 elements expecting more points run as 8-lane mini-chains */
+  double mini_expect; /* ProbMinHash1/3 elements expecting more points run as 4-lane mini-chains */
   int split_log2;     /* batched forms: sets of >= 2^split_log2 elements are split into chunks of
                          2^(split_log2-1) elements on separate workgroups (0: never; else 2..21).
                          Needs out_keys, out_val or out_id, whose rows hold the merged keys. */
@@ -174,7 +174,8 @@ int pmh_get_table(pmh_ctx* ctx, int which, double* out, uint32_t count);
  * key in_u[k] at point k+1 (PMH3 constants), 6 Lemire(m) label of that point,
  * 7 ProbMinHash1 fixed-point spacing of that point, 8 stream logarithm(in),
  * 9 inclusive prefix sum of in_u over each aligned group of 64 entries (the
- * chain-mode spacing scan; entries < 2^51), 10 the same over groups of 8. */
+ * chain-mode spacing scan; entries < 2^51), 10, 11, 12 the same over groups
+ * of 8, 4, 2 (the mini-chain scans). */
 int pmh_debug_eval(pmh_ctx* ctx, int what, const double* in, const uint64_t* in_u, double* out,
                    uint64_t* out_u, uint64_t n, void* stream);
 

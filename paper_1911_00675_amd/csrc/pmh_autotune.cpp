@@ -79,7 +79,13 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
             if (lds_bytes(c->variant, c->m, wv) <= c->lds_limit) add([&](Tuning& t) { t.waves = wv; });
           break;
         case 1:
-          for (double c0 : {1.0, 2.0, 3.0, 4.0, 6.0}) add([&](Tuning& t) { t.c0 = c0; });
+          for (double c0 : {1.0, 2.0, 3.0, 4.0, 6.0})
+            for (double g : {1.35, 2.0})
+              add([&](Tuning& t) {
+                t.c0 = c0;
+                t.grow = g;
+                t.max_rounds = g < 1.5 ? 8 : 4;
+              });
           break;
         case 2:
           for (double ce : {16.0, 32.0, 48.0, 96.0, 192.0}) add([&](Tuning& t) { t.chain_expect = ce; });

@@ -41,7 +41,7 @@ struct Tuning {
   int waves = 2;            // waves per workgroup
   int kmax_refresh = 8;     // element batches between stop-limit refreshes
   int blocks_per_cu = 0;    // persistent grid = CUs * this (0: occupancy limit)
-  double mini_expect = 48;  // ProbMinHash1/3: elements expecting more points go straight to 8-lane mini-chains
+  double mini_expect = 48;  // ProbMinHash1/3: elements expecting more points go straight to 4-lane mini-chains
                             // (at the default = chain_expect, minis take only lane-budget overflows)
   int split_log2 = 15;      // sets of >= 2^this elements run as chunks of 2^(this-1) (0: never split)
   double c0_split = 6.0;    // extra threshold margin of chunks (keeps the completion repair rare)

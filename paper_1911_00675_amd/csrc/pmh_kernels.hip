@@ -262,19 +262,25 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v, int lane) {
   const uint32_t hi = wave_incl_scan_u32((uint32_t)(v >> 26));
   return ((uint64_t)hi << 26) + lo;
 }
-// The same within aligned groups of 8 lanes (j = lane & 7).
-__device__ __forceinline__ uint32_t group8_incl_scan_u32(uint32_t x, int j) {
+// The same within aligned groups of G = 2, 4 or 8 lanes (j = lane & (G-1)).
+template <int G>
+__device__ __forceinline__ uint32_t group_incl_scan_u32(uint32_t x, int j) {
   uint32_t o = dpp_shr<1>(x);
   x += j >= 1 ? o : 0u;
-  o = dpp_shr<2>(x);
-  x += j >= 2 ? o : 0u;
-  o = dpp_shr<4>(x);
-  x += j >= 4 ? o : 0u;
+  if constexpr (G >= 4) {
+    o = dpp_shr<2>(x);
+    x += j >= 2 ? o : 0u;
+  }
+  if constexpr (G == 8) {
+    o = dpp_shr<4>(x);
+    x += j >= 4 ? o : 0u;
+  }
   return x;
 }
-__device__ __forceinline__ uint64_t group8_incl_scan_u64(uint64_t v, int j) {
-  const uint32_t lo = group8_incl_scan_u32((uint32_t)v & 0x3FFFFFFu, j);
-  const uint32_t hi = group8_incl_scan_u32((uint32_t)(v >> 26), j);
+template <int G>
+__device__ __forceinline__ uint64_t group_incl_scan_u64(uint64_t v, int j) {
+  const uint32_t lo = group_incl_scan_u32<G>((uint32_t)v & 0x3FFFFFFu, j);
+  const uint32_t hi = group_incl_scan_u32<G>((uint32_t)(v >> 26), j);
   return ((uint64_t)hi << 26) + lo;
 }
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int src) {
@@ -366,13 +372,27 @@ __device__ __forceinline__ void push_mini(Shared& sm, ChainEntry* q, uint32_t qc
   q[qcap - 1 - slot] = ChainEntry{p, i, tacc};
 }
 
+// ProbMinHash3 (Sec. 2.5): point i of an element of weight w lies in
+// [(i-1)/w, i/w), so a later round need not regenerate the points below Tprev.
+// Points 1..f with f = floor(w Tprev (1 - 2^-40)) end below Tprev by a relative
+// margin far above the rounding of their computed values (a few units of
+// 2^-53), so they are skipped and the round starts at point f + 1.  Returns
+// imax + 1 when every point of the stream lies below Tprev.
+template <int V>
+__device__ __forceinline__ uint32_t first_index(double w, double Tprev, uint32_t imax) {
+  if (V != 3 || !(Tprev > 0.0)) return 1;
+  const double f = floor(w * Tprev * (1.0 - 0x1p-40));
+  if (!(f >= 1.0)) return 1;
+  return f >= (double)imax ? imax + 1 : (uint32_t)f + 1;
+}
+
 // ------------------------------------------------------------- lane mode
 // Returns after the element's points below R.T are applied, or after pushing
 // the element to a chain queue.
 template <int V>
 __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint32_t p, double winv,
                                           uint64_t K, uint64_t kmax, uint64_t* keys, Shared& sm,
-                                          ChainEntry* q, int budget) {
+                                          ChainEntry* q, int budget, uint32_t i0) {
   const Tables& t = A.t;
   const uint32_t m = R.m;
   const LogCell* lt = R.lt;
@@ -401,8 +421,8 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
     }
   } else if constexpr (V == 3) {
     const double lam = t.scal[0], c1 = t.scal[1], c2 = t.scal[2], c3 = t.scal[3];
-    uint32_t i = 1;
-    uint64_t pb = pbase(K, 1);
+    uint32_t i = i0;
+    uint64_t pb = pbase(K, i0);
     for (int step = 0;; ++step, pb += kPointStep) {
       const double lb = winv * (double)(i - 1);
       if (!(lb < R.T)) return step;
@@ -594,14 +614,17 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
   }
 }
 
-// Mini-chain mode (ProbMinHash1/3): the wave is split into eight 8-lane
-// groups, each running one medium-length stream 8 consecutive points per
-// step and taking the next queued stream as soon as its own ends.
-template <int V>
+// Mini-chain mode (ProbMinHash1/3): the wave is split into groups of G lanes,
+// each running one medium-length stream G consecutive points per step and
+// taking the next queued stream as soon as its own ends.  Streams reach this
+// mode after the lane budget with a few points left, so narrow groups waste
+// fewer lanes on a stream's last step (4 lanes measured faster than 2 or 8).
+constexpr int kMiniLanes = 4;
+template <int V, int G>
 __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, ChainEntry* q, Shared& sm) {
   const Tables& t = A.t;
   const int lane = threadIdx.x & 63;
-  const int j = lane & 7, leader = lane & ~7, grp = lane >> 3;
+  const int j = lane & (G - 1), leader = lane & ~(G - 1), grp = lane / G;
   const uint32_t m = R.m, end = R.imax;
   const LogCell* lt = R.lt;
   const uint32_t mtail = sm.mtail;
@@ -635,7 +658,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
     uint64_t key = kEmptyKey, tl = 0;
     bool stop;
     if constexpr (V == 1) {
-      const uint64_t d = group8_incl_scan_u64(valid ? spacing_fixed(exp1(w0, lt)) : 0, j);
+      const uint64_t d = group_incl_scan_u64<G>(valid ? spacing_fixed(exp1(w0, lt)) : 0, j);
       tl = tacc + d;
       x = winv * fixed_value(tl);
       key = make_key(x, p);
@@ -649,8 +672,8 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
       }
     }
     const uint64_t smask = __ballot(stop);
-    const uint32_t bits = (uint32_t)(smask >> (grp * 8)) & 0xFFu;
-    const int first = __builtin_ctz(bits | 0x100u);
+    const uint32_t bits = (uint32_t)(smask >> (grp * G)) & ((1u << G) - 1u);
+    const int first = __builtin_ctz(bits | (1u << G));
     const bool apply = have && j < first && x >= R.Tprev && key < kmax;
     if (lane == 0) PMH_STAT(sm, kStMiniSteps, 1);
     if (have && j == 0) PMH_STAT(sm, kStMiniPts, first);
@@ -658,13 +681,13 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
       PMH_STAT(sm, kStApply, 1);
       lds_min(keys, lemire(w0, pb, m), key);
     }
-    const uint64_t tlast = shfl_u64(tl, leader + 7);
+    const uint64_t tlast = shfl_u64(tl, leader + G - 1);
     if (have) {
-      if (first < 8) {
+      if (first < G) {
         have = false;
       } else {
-        i0 += 8;
-        pb += 8ull * kPointStep;
+        i0 += G;
+        pb += (uint64_t)G * kPointStep;
         tacc = tlast;
       }
     }
@@ -692,7 +715,7 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
   }
   PMH_TOC(sm, kStCycChain, t_chain);
   PMH_TIC(t_mini);
-  if constexpr (V == 1 || V == 3) mini_pass<V>(A, R, keys, q, sm);
+  if constexpr (V == 1 || V == 3) mini_pass<V, kMiniLanes>(A, R, keys, q, sm);
   PMH_TOC(sm, kStCycMini, t_mini);
   PMH_TIC(t_bar);
   __syncthreads();
@@ -813,18 +836,20 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
       const double w = wc[k];
       if (!weight_ok(w)) continue;
       PMH_STAT(sm, kStElems, 1);
-      const double lam = w * Teff;  // expected points generated
+      const uint32_t i0 = first_index<V>(w, R.Tprev, R.imax);
+      if (i0 > R.imax) continue;
+      const double lam = w * (V == 3 ? Teff - R.Tprev : Teff);  // expected points generated
       if (lam > A.chain_expect) {
-        push_long(sm, q, p, 1, 0);
+        push_long(sm, q, p, i0, 0);
         continue;
       }
       if ((V == 1 || V == 3) && lam > A.mini_expect) {
-        push_mini(sm, q, qcap, p, 1, 0);
+        push_mini(sm, q, qcap, p, i0, 0);
         continue;
       }
       const double winv = 1.0 / w;
       const uint64_t K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
-      const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget);
+      const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget, i0);
 #ifdef PMH_STATS
       // wave-level cost of this element slot: the longest lane
       int mx = steps;
@@ -1279,12 +1304,17 @@ __global__ void k_debug(int what, const double* in, const uint64_t* in_u, double
   }
 }
 
-// Wave prefix sums of the fixed-point spacings (64-lane chains: what 9; 8-lane
-// groups: what 10), every lane participating; inputs beyond n count as 0.
+// Wave prefix sums of the fixed-point spacings (64-lane chains: what 9;
+// mini-chain groups of 8, 4, 2 lanes: what 10, 11, 12), every lane
+// participating; inputs beyond n count as 0.
 __global__ void k_debug_scan(int what, const uint64_t* in_u, uint64_t* out_u, uint64_t n) {
   const uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
   const uint64_t v = k < n ? in_u[k] : 0;
-  const uint64_t r = what == 9 ? wave_incl_scan_u64(v, threadIdx.x & 63) : group8_incl_scan_u64(v, threadIdx.x & 7);
+  const int lane = threadIdx.x & 63;
+  const uint64_t r = what == 9    ? wave_incl_scan_u64(v, lane)
+                     : what == 10 ? group_incl_scan_u64<8>(v, lane & 7)
+                     : what == 11 ? group_incl_scan_u64<4>(v, lane & 3)
+                                  : group_incl_scan_u64<2>(v, lane & 1);
   if (k < n) out_u[k] = r;
 }
 
@@ -1388,7 +1418,7 @@ hipError_t launch_debug_eval(int what, const double* in, const uint64_t* in_u, d
                              uint64_t n, uint32_t m, int variant, Tables t, hipStream_t s) {
   (void)variant;
   if (n == 0) return hipSuccess;
-  if (what == 9 || what == 10) {
+  if (what >= 9) {
     hipLaunchKernelGGL(k_debug_scan, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, what, in_u, out_u, n);
     return hipGetLastError();
   }

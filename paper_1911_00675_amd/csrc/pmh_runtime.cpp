@@ -190,6 +190,11 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   c->seedhash = host_mix64(seed);
   c->m = m;
   c->variant = variant;
+  if (variant == 3) {  // later rounds resume near the previous threshold: thinner rounds pay
+    c->tune.c0 = 2.0;
+    c->tune.grow = 1.35;
+    c->tune.max_rounds = 8;
+  }
   c->device = dev;
   c->lds_limit = lim;
   hipDeviceProp_t prop;
@@ -455,7 +460,7 @@ int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
 
 int pmh_debug_eval(pmh_ctx* c, int what, const double* in, const uint64_t* in_u, double* out, uint64_t* out_u,
                    uint64_t n, void* stream) {
-  if (!c || what < 0 || what > 10) return PMH_ERR_ARG;
+  if (!c || what < 0 || what > 12) return PMH_ERR_ARG;
   const bool uses_u = (what >= 3 && what <= 7) || what >= 9;
   const bool out_is_u = what == 4 || what == 6 || what == 7 || what >= 9;
   if ((uses_u && !in_u) || (!uses_u && !in) || (out_is_u && !out_u) || (!out_is_u && !out)) return PMH_ERR_ARG;

@@ -227,7 +227,7 @@ class Context:
         torch = _torch()
         n = int(x.size)
         uses_u = 3 <= what <= 7 or what >= 9
-        out_u = what in (4, 6, 7, 9, 10)
+        out_u = what in (4, 6, 7, 9, 10, 11, 12)
         xin = to_device(x.astype(np.uint64) if uses_u else x.astype(np.float64))
         o = torch.empty(n, dtype=torch.int64 if out_u else torch.float64, device="cuda")
         rc = lib().pmh_debug_eval(self._c, what, None if uses_u else ctypes.c_void_p(xin.data_ptr()),

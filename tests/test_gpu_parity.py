@@ -74,11 +74,11 @@ def test_primitives_bitwise(pmh):
     assert np.array_equal(ctx.debug_eval(8, xs).view(np.uint64),
                           np.array([O.stream_log(v) for v in xs]).view(np.uint64))
     assert np.array_equal(ctx.table(9, 512).view(np.uint64), O.stream_log_table().view(np.uint64))
-    # wave prefix sums of fixed-point spacings (chains: 64 lanes, mini-chains: 8)
+    # wave prefix sums of fixed-point spacings (chains: 64 lanes, mini-chains: 8, 4, 2)
     sp_in = rng.integers(0, 2**51, size=64 * 300, dtype=np.uint64)
     sp_in[:64] = np.uint64(2**51 - 1)  # largest spacings
     sp_in[64:128] = 0
-    for what, g in ((9, 64), (10, 8)):
+    for what, g in ((9, 64), (10, 8), (11, 4), (12, 2)):
         want = np.cumsum(sp_in.reshape(-1, g), axis=1, dtype=np.uint64).reshape(-1)
         assert np.array_equal(ctx.debug_eval(what, sp_in), want), what
         tail = sp_in[:100]  # a partial last group: missing entries count as 0
@@ -228,8 +228,15 @@ def test_schedule_invariance(pmh, variant):
     configs = [dict(), dict(c0=-6.0, grow=1.3, max_rounds=12), dict(max_rounds=1), dict(chain_expect=0.0),
                dict(chain_expect=1e9, mini_expect=1e9, lane_budget=1000000), dict(lane_budget=1),
                dict(mini_expect=0.0), dict(mini_expect=0.0, chain_expect=1e9), dict(waves=1), dict(waves=2),
+               dict(lane_budget=1, waves=1),
                dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0),
-               dict(kmax_refresh=3, max_rounds=1)]
+               dict(kmax_refresh=3, max_rounds=1),
+               # many thin rounds (ProbMinHash3 resumes each element near the
+               # previous threshold) in every mode
+               dict(c0=-3.0, grow=1.05, max_rounds=60),
+               dict(c0=-3.0, grow=1.05, max_rounds=60, chain_expect=0.0),
+               dict(c0=-3.0, grow=1.05, max_rounds=60, mini_expect=0.0, chain_expect=1e9),
+               dict(c0=-3.0, grow=1.05, max_rounds=60, chain_expect=1e9, mini_expect=1e9, lane_budget=1000000)]
     for cfg in configs:
         ctx.set_tuning(**cfg)
         sig, st = _keys(ctx, b)
