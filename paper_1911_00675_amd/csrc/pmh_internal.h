@@ -71,6 +71,7 @@ struct HashArgs {
   Tables t;
   double c0, grow, chain_expect, mini_expect;
   int max_rounds, lane_budget, kmax_refresh;
+  uint32_t qcap;             // chain queue entries in LDS (>= one batch)
   uint32_t* status;          // device status word
   const uint32_t* order;     // work list (set indices), heavy first
   uint32_t* counter;         // work counters (zeroed by the order kernel)
@@ -95,7 +96,12 @@ hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size
 hipError_t launch_hash_one(int variant, const HashArgs& a, uint64_t set, int waves, size_t lds,
                            hipStream_t s);
 hipError_t occupancy(int variant, int waves, size_t lds, int* blocks_per_cu);
-size_t lds_bytes(int variant, uint32_t m, int waves);   // dynamic LDS of k_hash_*
+// A workgroup reads its set in batches of batch_size(waves) elements; its
+// chain queue holds qcap >= one batch of entries (launches size it to the LDS
+// left at the register-limited occupancy, up to 8 batches).
+uint32_t batch_size(int waves);
+size_t lds_bytes_q(int variant, uint32_t m, int waves, uint32_t qcap);  // dynamic LDS of k_hash_*
+size_t lds_bytes(int variant, uint32_t m, int waves);   // the same with a queue of 2 batches (m range check)
 size_t lds_static_bytes();                                // its static LDS
 hipError_t launch_estimate(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB,
                            const uint32_t* idxB, uint32_t m, uint64_t pairs, uint32_t* counts,

@@ -994,7 +994,7 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
   unsigned char* base = dyn + kLogCells * sizeof(LogCell);
   keys = reinterpret_cast<uint64_t*>(base);
   q = reinterpret_cast<ChainEntry*>(base + (size_t)m * 8);
-  qcap = 2 * kEpt * NW * 64;
+  qcap = A.qcap;
   fy = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(base + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry))
                           : nullptr;
   const LogCell* src = reinterpret_cast<const LogCell*>(A.t.ltab);
@@ -1321,29 +1321,42 @@ __global__ void k_debug_scan(int what, const uint64_t* in_u, uint64_t* out_u, ui
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-size_t lds_bytes(int variant, uint32_t m, int waves) {
-  const size_t qcap = 2 * kEpt * (size_t)waves * 64;
-  size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + qcap * sizeof(ChainEntry);
+uint32_t batch_size(int waves) { return kEpt * (uint32_t)waves * 64; }
+
+size_t lds_bytes_q(int variant, uint32_t m, int waves, uint32_t qcap) {
+  size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry);
   if (variant == 2 || variant == 4) b += (size_t)waves * m * 2;
   return b;
 }
+
+size_t lds_bytes(int variant, uint32_t m, int waves) { return lds_bytes_q(variant, m, waves, 2 * batch_size(waves)); }
 
 size_t lds_static_bytes() {
   return sizeof(Shared) + 64;  // the per-workgroup static block (k_hash_*) plus alignment slack
 }
 
+// The kernels carve the chain queue (a.qcap entries) out of the dynamic LDS and
+// fill it up to one batch beyond the flush point: refuse launches whose queue
+// or LDS is smaller than that layout needs.
+template <int V, int NW>
+static bool shape_ok(const HashArgs& a, size_t lds) {
+  return a.qcap >= batch_size(NW) && lds >= lds_bytes_q(V, a.m, NW, a.qcap);
+}
 template <int V, int NW>
 static hipError_t launch_hash_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (!shape_ok<V, NW>(a, lds)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_hash_persistent<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
   return hipGetLastError();
 }
 template <int V, int NW>
 static hipError_t launch_finish_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (!shape_ok<V, NW>(a, lds)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_big_finish<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
   return hipGetLastError();
 }
 template <int V, int NW>
 static hipError_t launch_one_t(const HashArgs& a, uint64_t set, size_t lds, hipStream_t s) {
+  if (!shape_ok<V, NW>(a, lds)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_hash_one<V, NW>), dim3(1), dim3(NW * 64), lds, s, a, set);
   return hipGetLastError();
 }

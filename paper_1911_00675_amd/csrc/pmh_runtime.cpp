@@ -51,6 +51,36 @@ int effective_waves(const pmh_ctx* c) {
   return w;
 }
 
+static int waves_slot(int waves) { return waves == 1 ? 0 : waves == 2 ? 1 : 2; }
+
+// The chain queue takes the LDS left over at the register-limited occupancy
+// (the workgroups per CU with a one-batch queue), in steps of 32 entries and
+// up to 8 batches: a bigger queue means fewer mid-round chain passes.
+void plan_queues(pmh_ctx* c) {
+  for (int waves : {1, 2, 4}) {
+    const uint32_t batch = batch_size(waves);
+    uint32_t best = 2 * batch;
+    int occ0 = 0;
+    const size_t l0 = lds_bytes_q(c->variant, c->m, waves, batch);
+    if (l0 <= c->lds_limit && occupancy(c->variant, waves, l0, &occ0) == hipSuccess && occ0 >= 1) {
+      for (uint32_t q = 8 * batch; q >= batch; q -= 32) {
+        const size_t l = lds_bytes_q(c->variant, c->m, waves, q);
+        int occ = 0;
+        if (l <= c->lds_limit && occupancy(c->variant, waves, l, &occ) == hipSuccess && occ >= occ0) {
+          best = q;
+          break;
+        }
+      }
+    }
+    c->qcap[waves_slot(waves)] = best;
+  }
+}
+
+size_t launch_lds(const pmh_ctx* c, int waves, uint32_t* qcap) {
+  *qcap = c->qcap[waves_slot(waves)];
+  return lds_bytes_q(c->variant, c->m, waves, *qcap);
+}
+
 void free_work(WorkBuf* wb) {
   if (wb->order) (void)hipFree(wb->order);
   if (wb->small) (void)hipFree(wb->small);
@@ -123,7 +153,8 @@ int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, i
                     hipEvent_t ev0, hipEvent_t ev1) {
   if (a.num_sets == 0) return PMH_OK;
   if (waves <= 0) waves = effective_waves(c);
-  const size_t lds = lds_bytes(c->variant, c->m, waves);
+  HashArgs la = a;
+  const size_t lds = launch_lds(c, waves, &la.qcap);
   if (per_cu <= 0) per_cu = c->tune.blocks_per_cu;
   if (per_cu <= 0) {
     if (occupancy(c->variant, waves, lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
@@ -135,11 +166,11 @@ int enqueue_batched(pmh_ctx* c, const HashArgs& a, WorkBuf* wb, hipStream_t s, i
   if (launch_order(a.off, a.num_sets, a.split_log2, wa, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (a.split_log2 && launch_big_init(wa, a.m, a.big_keys, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PMH_ERR_DEVICE;
-  if (launch_hash(c->variant, a, waves, (int)grid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (launch_hash(c->variant, la, waves, (int)grid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return PMH_ERR_DEVICE;
   if (a.split_log2) {
     const uint64_t fgrid = std::min<uint64_t>((uint64_t)c->num_cu * (uint64_t)per_cu, a.num_sets);
-    if (launch_big_finish(c->variant, a, waves, (int)fgrid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
+    if (launch_big_finish(c->variant, la, waves, (int)fgrid, lds, s) != hipSuccess) return PMH_ERR_DEVICE;
   }
   return PMH_OK;
 }
@@ -203,6 +234,7 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
     return PMH_ERR_DEVICE;
   }
   c->num_cu = prop.multiProcessorCount;
+  plan_queues(c);
   // constant tables: 7 arrays of m+1 doubles + expm1 (19) + scalars (8) + log cells (512)
   const size_t nd = 7 * (size_t)(m + 1) + 19 + 8 + 512;
   if (hipMalloc(&c->table_mem, nd * sizeof(double)) != hipSuccess) {
@@ -318,7 +350,7 @@ int pmh_hash_sets_plain(pmh_ctx* c, const uint64_t* ids, const double* w, const 
   DeviceGuard g(c->device);
   HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, nullptr);
   const int waves = effective_waves(c);
-  const size_t lds = lds_bytes(c->variant, c->m, waves);
+  const size_t lds = launch_lds(c, waves, &a.qcap);
   for (uint64_t s = 0; s < num_sets; ++s)
     if (launch_hash_one(c->variant, a, s, waves, lds, (hipStream_t)stream) != hipSuccess) return PMH_ERR_DEVICE;
   return PMH_OK;

@@ -61,6 +61,7 @@ struct pmh_ctx {
   int device = 0;
   int num_cu = 1;
   size_t lds_limit = 65536;
+  uint32_t qcap[3] = {128, 256, 512};  // chain queue entries for 1, 2, 4 waves per workgroup
   void* table_mem = nullptr;
   pmh::Tables t{};
   uint32_t* status = nullptr;
@@ -79,6 +80,10 @@ struct pmh_ctx {
 
 namespace pmh {
 int effective_waves(const pmh_ctx* c);
+// Dynamic LDS of a hash launch with `waves` per workgroup; *qcap receives the
+// chain queue capacity to pass in HashArgs.
+size_t launch_lds(const pmh_ctx* c, int waves, uint32_t* qcap);
+void plan_queues(pmh_ctx* c);
 int ensure_work(pmh_ctx* c, WorkBuf* wb, uint64_t num_sets);
 HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
                    uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, const WorkBuf* wb);

@@ -365,7 +365,8 @@ int pmh_server_create(pmh_ctx* c, int slots, uint64_t slot_elems, uint32_t slot_
   S->epoch = Clock::now();
   S->waves = effective_waves(c);
   int occ = 1;
-  if (occupancy(c->variant, S->waves, lds_bytes(c->variant, c->m, S->waves), &occ) != hipSuccess || occ < 1) occ = 1;
+  uint32_t qcap = 0;
+  if (occupancy(c->variant, S->waves, launch_lds(c, S->waves, &qcap), &occ) != hipSuccess || occ < 1) occ = 1;
   S->per_cu = std::max(1, occ / slots);  // each slot's share of the CUs' workgroup (LDS) capacity
   S->slots.resize(slots);
   int rc = PMH_OK;
