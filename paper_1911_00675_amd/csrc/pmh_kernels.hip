@@ -73,19 +73,27 @@ __device__ __forceinline__ uint64_t pbase(uint64_t K, uint32_t i) {
   return K + (uint64_t)((i << 8) + 1u) * kPhi;
 }
 __device__ __forceinline__ uint64_t word(uint64_t pb, uint32_t t) { return mix64(pb + (uint64_t)t * kPhi); }
-__device__ __forceinline__ double u32v(uint64_t w) { return (double)(uint32_t)(w >> 32) * 0x1p-32; }
+// The high half of w as an opaque 32-bit register value: the compiler would
+// otherwise widen the u32 -> f64 conversions below to 64-bit ones that add a
+// zero high part (an extra fp64 add each, kept under strict IEEE semantics).
+__device__ __forceinline__ uint32_t hi32(uint64_t w) {
+  uint32_t h = (uint32_t)(w >> 32);
+  asm("" : "+v"(h));
+  return h;
+}
+__device__ __forceinline__ double u32v(uint64_t w) { return (double)hi32(w) * 0x1p-32; }
 // ((w >> 32) + 1) 2^-32, exact (the sum is at most 2^32)
-__device__ __forceinline__ double upos32(uint64_t w) { return ((double)(uint32_t)(w >> 32) + 1.0) * 0x1p-32; }
+__device__ __forceinline__ double upos32(uint64_t w) { return ((double)hi32(w) + 1.0) * 0x1p-32; }
 // floor(s 2^32) of a spacing 0 <= s < 2^20, exact: the integral value t < 2^52
 // is the low 52 bits of t + 2^52
 __device__ __forceinline__ uint64_t spacing_fixed(double s) {
   const double t = trunc(s * 0x1p32);
   return (uint64_t)__double_as_longlong(t + 0x1p52) & 0xFFFFFFFFFFFFFull;
 }
-// T 2^-32 of the fixed-point accumulator, rounded once (exact below 2^52)
+// T 2^-32 of the fixed-point accumulator as the nearest double: the fma
+// rounds hi + lo 2^-32 once (exact below 2^53)
 __device__ __forceinline__ double fixed_value(uint64_t T) {
-  if (T < (1ull << 52)) return (__longlong_as_double((long long)(T | 0x4330000000000000ull)) - 0x1p52) * 0x1p-32;
-  return (double)T * 0x1p-32;
+  return fma((double)(uint32_t)T, 0x1p-32, (double)hi32(T));
 }
 __device__ __forceinline__ double u53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
 
@@ -550,7 +558,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
         key = make_key(x, p);
       }
     }
-    const uint64_t stopmask = __ballot(stop);
+    const uint64_t stopmask = __builtin_amdgcn_ballot_w64(stop);
     const int first = stopmask ? __builtin_ctzll(stopmask) : 64;
     const bool active = lane < first;
     const bool apply = active && x >= R.Tprev && key < kmax;
@@ -650,7 +658,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
         if (j == 0) PMH_STAT(sm, kStMiniElems, 1);
       }
     }
-    if (__ballot(have) == 0) break;
+    if (__builtin_amdgcn_ballot_w64(have) == 0) break;
     const uint32_t i = i0 + (uint32_t)j;
     const bool valid = have && i <= end;
     const uint64_t w0 = mix64(pb);
@@ -671,7 +679,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
         key = make_key(x, p);
       }
     }
-    const uint64_t smask = __ballot(stop);
+    const uint64_t smask = __builtin_amdgcn_ballot_w64(stop);
     const uint32_t bits = (uint32_t)(smask >> (grp * G)) & ((1u << G) - 1u);
     const int first = __builtin_ctz(bits | (1u << G));
     const bool apply = have && j < first && x >= R.Tprev && key < kmax;
