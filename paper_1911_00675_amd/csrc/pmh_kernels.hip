@@ -145,6 +145,18 @@ __device__ __forceinline__ double spec_expm1(double t, const double* c) {
 struct LogCell {
   double inv, L;
 };
+// a*b + c as the three-address VOP3 fma when kAsm: with a constant addend the
+// compiler otherwise picks the two-address fmac and copies the constant every
+// time (the hot ProbMinHash1/2 streams use it; elsewhere the plain builtin
+// schedules better).
+template <bool kAsm>
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  if constexpr (!kAsm) return __builtin_fma(a, b, c);
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+template <bool kAsm = true>
 __device__ __forceinline__ double stream_log(double x, const LogCell* tab) {
   const uint64_t b = (uint64_t)__double_as_longlong(x);
   int e = (int)((b >> 52) & 0x7FF) - 1023;
@@ -156,17 +168,20 @@ __device__ __forceinline__ double stream_log(double x, const LogCell* tab) {
   const double y = __longlong_as_double((long long)(mant | (1023ull << 52)));
   const double r = __builtin_fma(y, c.inv, -1.0);
   double q = 1.0 / 8.0;
-  q = __builtin_fma(q, r, -1.0 / 7.0);
-  q = __builtin_fma(q, r, 1.0 / 6.0);
-  q = __builtin_fma(q, r, -1.0 / 5.0);
+  q = fma3<kAsm>(q, r, -1.0 / 7.0);
+  q = fma3<kAsm>(q, r, 1.0 / 6.0);
+  q = fma3<kAsm>(q, r, -1.0 / 5.0);
   q = __builtin_fma(q, r, 1.0 / 4.0);
-  q = __builtin_fma(q, r, -1.0 / 3.0);
+  q = fma3<kAsm>(q, r, -1.0 / 3.0);
   q = __builtin_fma(q, r, 1.0 / 2.0);
   const double l1p = __builtin_fma(-(r * r), q, r);
   const double de = (double)e;
   return de * kLn2Hi + (de * kLn2Lo + (c.L + l1p));
 }
-__device__ __forceinline__ double exp1(uint64_t w, const LogCell* tab) { return 0.0 - stream_log(upos32(w), tab); }
+template <bool kAsm = true>
+__device__ __forceinline__ double exp1(uint64_t w, const LogCell* tab) {
+  return 0.0 - stream_log<kAsm>(upos32(w), tab);
+}
 
 // Rejection part of the truncated-exponential sampler (Sec. 2.8).
 __device__ __attribute__((noinline)) double te_slow(uint64_t pb, double lam, double c1, double c2,
@@ -474,7 +489,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         if (i < m)
           x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
         else
-          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(w0, lt));
+          x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
       }
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
       const uint32_t j = (i - 1) + lemire(w0, pb, m - i + 1);
@@ -554,7 +569,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
         if (i < m)
           x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
         else
-          x = winv * (t.gam[m - 1] + t.scal[4] * exp1(w0, lt));
+          x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
         key = make_key(x, p);
       }
     }
