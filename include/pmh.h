@@ -190,8 +190,12 @@ int pmh_debug_eval(pmh_ctx* ctx, int what, const double* in, const uint64_t* in_
  * 2^20, so any set fits) and slot_sets requests per slot; with a non-zero
  * hbm_budget_bytes the slots' device buffers are sized to fit it; each
  * slot's persistent grid is its share of the CUs' workgroup (LDS) capacity.
- * When every slot is in flight a submission waits (back-pressure).  Results
- * are identical to pmh_hash_sets on the same set. */
+ * A batch finishes with its slowest set, so requests of >= 2^11 elements run
+ * as 1,024-element chunks on separate workgroups (unless the context's
+ * split_log2 is 0).  Creation runs one set through every slot (first use of a
+ * stream costs milliseconds).  When every slot is in flight a submission
+ * waits (back-pressure).  Results are identical to pmh_hash_sets on the same
+ * set. */
 int pmh_server_create(pmh_ctx* ctx, int slots, uint64_t slot_elems, uint32_t slot_sets,
                       uint64_t hbm_budget_bytes, pmh_server** out);
 /* Copy a request in ([host] ids, weights of n <= 2^20 elements); *ticket
@@ -213,9 +217,12 @@ int pmh_server_fetch(pmh_server* s, uint64_t ticket, uint32_t* idx, double* val,
 int pmh_server_replay(pmh_server* s, const uint64_t* ids, const double* weights, const uint64_t* offsets,
                       uint64_t num, const double* arrival, double* latency, uint32_t* out_idx,
                       uint64_t* out_id, double* wall);
-/* Counters: [0] batches launched, [1] requests done, [2] max requests in one
- * batch, [3] max concurrent slots busy, [4] requests that waited for a slot. */
-int pmh_server_stats(pmh_server* s, uint64_t* out5);
+/* Counters into out8[8]: [0] batches launched, [1] requests done, [2] max
+ * requests in one batch, [3] max concurrent slots busy, [4] requests that
+ * waited for a slot; dispatcher timing in microseconds: [5] longest launch
+ * (copies and kernels enqueued), [6] longest finish (results handed out),
+ * [7] longest dispatcher loop iteration. */
+int pmh_server_stats(pmh_server* s, uint64_t* out8);
 void pmh_server_destroy(pmh_server* s);
 
 #ifdef __cplusplus

@@ -90,6 +90,14 @@ hipError_t launch_init_tables(int variant, uint32_t m, Tables t, hipStream_t s);
 hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t split_log2, const WorkArgs& w,
                         uint32_t* status, hipStream_t s);
 hipError_t launch_big_init(const WorkArgs& w, uint32_t m, uint64_t* big_keys, hipStream_t s);
+// Up to three copies of n[g] 32-bit words (n = 0: unused), between device
+// memory and device-mapped pinned host memory.
+struct CopySegs {
+  const uint32_t* src[3];
+  uint32_t* dst[3];
+  uint64_t n[3];
+};
+hipError_t launch_copy_words(const CopySegs& c, hipStream_t s);
 hipError_t launch_big_finish(int variant, const HashArgs& a, int waves, int grid, size_t lds, hipStream_t s);
 hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size_t lds,
                        hipStream_t s);

@@ -1180,6 +1180,18 @@ __global__ __launch_bounds__(1024) void k_order(const uint64_t* off, uint64_t nu
   }
 }
 
+// Serving copies between device buffers and pinned host memory
+// (device-mapped aliases): up to three segments of 32-bit words.  A kernel
+// rather than asynchronous copy calls, which were seen to hold the calling
+// thread for up to ~10 ms.
+__global__ __launch_bounds__(256) void k_copy_words(CopySegs c) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+    for (uint64_t k = t0; k < c.n[g]; k += stride) c.dst[g][k] = c.src[g][k];
+}
+
 // Global keys of the split sets start empty.
 __global__ __launch_bounds__(256) void k_big_init(const uint32_t* order, const uint32_t* meta, uint32_t m,
                                                   uint64_t* big_keys) {
@@ -1427,6 +1439,14 @@ hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t split_l
 
 hipError_t launch_big_init(const WorkArgs& w, uint32_t m, uint64_t* big_keys, hipStream_t s) {
   hipLaunchKernelGGL(k_big_init, dim3(512), dim3(256), 0, s, w.order, w.meta, m, big_keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_words(const CopySegs& c, hipStream_t s) {
+  const uint64_t n = std::max(c.n[0], std::max(c.n[1], c.n[2]));
+  if (n == 0) return hipSuccess;
+  const uint64_t blocks = std::min<uint64_t>((n + 1023) / 1024, 2048);
+  hipLaunchKernelGGL(k_copy_words, dim3((uint32_t)blocks), dim3(256), 0, s, c);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ namespace {
 struct Request {
   uint64_t ticket = 0;
   uint32_t n = 0;
-  const uint64_t* src_ids = nullptr;  // pinned source (replay): copied to the device directly
+  const uint64_t* src_ids = nullptr;  // pinned source (replay), device-mapped alias: read by the copy kernel
   const double* src_w = nullptr;
   uint64_t fill_off = 0;              // element offset of the request in its slot
   uint32_t* dst_idx = nullptr;  // result destinations (replay) ...
@@ -56,6 +56,29 @@ struct Request {
 
 enum SlotState { kFree, kOpen, kFlight };
 
+// Copy kernels between device buffers and device-mapped pinned host memory
+// (8-byte elements; dst/src pairs b and c may be null).
+hipError_t copy64(const void* sa, void* da, uint64_t na, const void* sb, void* db, uint64_t nb, const void* sc,
+                  void* dc, uint64_t nc, hipStream_t s) {
+  CopySegs g{{(const uint32_t*)sa, (const uint32_t*)sb, (const uint32_t*)sc},
+             {(uint32_t*)da, (uint32_t*)db, (uint32_t*)dc},
+             {2 * na, sb ? 2 * nb : 0, sc ? 2 * nc : 0}};
+  return launch_copy_words(g, s);
+}
+
+// Single-writer maximum (the dispatcher thread).
+void raise_max(std::atomic<uint64_t>& a, uint64_t v) {
+  if (v > a.load(std::memory_order_relaxed)) a.store(v, std::memory_order_relaxed);
+}
+
+// A batch finishes with its slowest set, so the server splits requests far
+// more finely than the batched throughput forms do: sets of >= 2^11 elements
+// run as 1,024-element chunks on separate workgroups (unless the context
+// disables splitting).  At 50,000 requests/s of 10..10^5 elements this
+// measured p99 0.5 ms against 5-25 ms with 2^15.
+constexpr uint32_t kServeSplitLog2 = 11;
+uint32_t serve_split(const pmh_ctx* c) { return c->tune.split_log2 > 0 ? kServeSplitLog2 : 0u; }
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
@@ -68,6 +91,13 @@ struct Slot {
   double* d_val = nullptr;
   uint64_t* h_ids = nullptr;
   double* h_w = nullptr;
+  // device-mapped aliases of the pinned buffers (the copy kernels use them)
+  const uint64_t* dh_ids = nullptr;
+  const double* dh_w = nullptr;
+  const uint64_t* dh_off = nullptr;
+  uint32_t* dh_idx = nullptr;
+  uint64_t* dh_id = nullptr;
+  double* dh_val = nullptr;
   uint64_t* h_off = nullptr;
   uint32_t* h_idx = nullptr;
   uint64_t* h_id = nullptr;
@@ -119,10 +149,22 @@ int alloc_slot_buffers(Slot& s, uint64_t elems, uint32_t sets, uint32_t m) {
                   hipHostMalloc(&s.h_idx, r * 4, hipHostMallocDefault) == hipSuccess &&
                   hipHostMalloc(&s.h_id, r * 8, hipHostMallocDefault) == hipSuccess &&
                   hipHostMalloc(&s.h_val, r * 8, hipHostMallocDefault) == hipSuccess;
-  if (!ok) {
+  void* a[6] = {};
+  if (!ok || hipHostGetDevicePointer(&a[0], s.h_ids, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&a[1], s.h_w, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&a[2], s.h_off, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&a[3], s.h_idx, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&a[4], s.h_id, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&a[5], s.h_val, 0) != hipSuccess) {
     free_slot_buffers(s);
     return PMH_ERR_OOM;
   }
+  s.dh_ids = (const uint64_t*)a[0];
+  s.dh_w = (const double*)a[1];
+  s.dh_off = (const uint64_t*)a[2];
+  s.dh_idx = (uint32_t*)a[3];
+  s.dh_id = (uint64_t*)a[4];
+  s.dh_val = (double*)a[5];
   s.elems_cap = elems;
   s.sets_cap = sets;
   return PMH_OK;
@@ -144,7 +186,13 @@ struct pmh_server {
   int per_cu = 1;
   int waves = 2;
   int in_flight = 0;
-  uint64_t st_batches = 0, st_done = 0, st_max_batch = 0, st_max_busy = 0, st_waited = 0;
+  uint64_t st_done = 0, st_max_busy = 0, st_waited = 0;  // guarded by mu
+  // written by the dispatcher thread only (read by pmh_server_stats):
+  // batches, largest batch, and its timing in microseconds (longest launch:
+  // copies and kernels enqueued; longest finish: results handed out;
+  // longest loop iteration)
+  std::atomic<uint64_t> st_batches{0}, st_max_batch{0};
+  std::atomic<uint64_t> st_max_launch_us{0}, st_max_finish_us{0}, st_max_iter_us{0};
   int fatal = PMH_OK;
 };
 
@@ -204,23 +252,22 @@ void submit_internal(pmh_server* S, Request* r, const uint64_t* ids, const doubl
 
 // Host->device copy of the batch's ids and weights: runs of requests whose
 // sources are contiguous (staging, or consecutive requests of a pinned
-// replay buffer) go in one copy each.
+// replay buffer) go in one copy kernel each.
 int copy_in(Slot& sl) {
   const uint64_t* run_ids = nullptr;
   const double* run_w = nullptr;
   uint64_t run_dst = 0, run_len = 0;
   auto flush = [&]() -> bool {
     if (!run_len) return true;
-    const bool ok =
-        hipMemcpyAsync(sl.d_ids + run_dst, run_ids, run_len * 8, hipMemcpyHostToDevice, sl.stream) == hipSuccess &&
-        hipMemcpyAsync(sl.d_w + run_dst, run_w, run_len * 8, hipMemcpyHostToDevice, sl.stream) == hipSuccess;
+    const bool ok = copy64(run_ids, sl.d_ids + run_dst, run_len, run_w, sl.d_w + run_dst, run_len, nullptr, nullptr, 0,
+                           sl.stream) == hipSuccess;
     run_len = 0;
     return ok;
   };
   for (Request* r : sl.batch) {
     if (!r->n) continue;
-    const uint64_t* si = r->src_ids ? r->src_ids : sl.h_ids + r->fill_off;
-    const double* sw = r->src_ids ? r->src_w : sl.h_w + r->fill_off;
+    const uint64_t* si = r->src_ids ? r->src_ids : sl.dh_ids + r->fill_off;
+    const double* sw = r->src_ids ? r->src_w : sl.dh_w + r->fill_off;
     if (run_len && si == run_ids + run_len && sw == run_w + run_len && r->fill_off == run_dst + run_len) {
       run_len += r->n;
       continue;
@@ -260,6 +307,15 @@ void finish(pmh_server* S, Slot& sl) {
   S->in_flight--;
 }
 
+// Signatures of nb sets to the slot's pinned result buffers.
+hipError_t out_copy(Slot& sl, uint64_t nb, uint32_t m) {
+  const uint64_t r = nb * m;
+  CopySegs g{{(const uint32_t*)sl.d_idx, (const uint32_t*)sl.d_id, (const uint32_t*)sl.d_val},
+             {sl.dh_idx, (uint32_t*)sl.dh_id, (uint32_t*)sl.dh_val},
+             {r, 2 * r, 2 * r}};
+  return launch_copy_words(g, sl.stream);
+}
+
 int launch(pmh_server* S, Slot& sl) {
   pmh_ctx* c = S->ctx;
   const uint32_t m = c->m;
@@ -272,18 +328,48 @@ int launch(pmh_server* S, Slot& sl) {
   }
   if (ensure_work(c, &sl.work, nb)) return PMH_ERR_OOM;
   if (copy_in(sl) != PMH_OK ||
-      hipMemcpyAsync(sl.d_off, sl.h_off, (nb + 1) * 8, hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+      copy64(sl.dh_off, sl.d_off, nb + 1, nullptr, nullptr, 0, nullptr, nullptr, 0, sl.stream) != hipSuccess)
     return PMH_ERR_DEVICE;
   HashArgs a = make_args(c, sl.d_ids, sl.d_w, sl.d_off, nb, sl.d_idx, sl.d_val, sl.d_id, nullptr, &sl.work);
+  a.split_log2 = serve_split(c);
   const int rc = enqueue_batched(c, a, &sl.work, sl.stream, S->per_cu, S->waves);
   if (rc) return rc;
-  if (hipMemcpyAsync(sl.h_idx, sl.d_idx, nb * m * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-      hipMemcpyAsync(sl.h_id, sl.d_id, nb * m * 8, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-      hipMemcpyAsync(sl.h_val, sl.d_val, nb * m * 8, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-      hipEventRecord(sl.ev, sl.stream) != hipSuccess)
+  if (out_copy(sl, nb, m) != hipSuccess || hipEventRecord(sl.ev, sl.stream) != hipSuccess) return PMH_ERR_DEVICE;
+  S->st_batches.fetch_add(1, std::memory_order_relaxed);
+  raise_max(S->st_max_batch, nb);
+  return PMH_OK;
+}
+
+// The first copies and kernel launches on a new stream cost milliseconds
+// (hardware queue and code set-up); left to the first requests they build a
+// backlog that takes over a thousand requests to drain.  One set of
+// 2^split unit-weight elements (split into chunks when splitting is on) runs
+// every step of launch() on the slot's stream at creation instead.
+int warm_slot(pmh_server* S, Slot& sl) {
+  pmh_ctx* c = S->ctx;
+  const uint32_t m = c->m;
+  const uint32_t sl2 = serve_split(c);
+  const uint64_t n = std::min<uint64_t>(sl.elems_cap, sl2 > 0 ? (1ull << sl2) : 64);
+  for (uint64_t k = 0; k < n; ++k) {
+    sl.h_ids[k] = k;
+    sl.h_w[k] = 1.0;
+  }
+  sl.h_off[0] = 0;
+  sl.h_off[1] = n;
+  if (copy64(sl.dh_ids, sl.d_ids, n, sl.dh_w, sl.d_w, n, sl.dh_off, sl.d_off, 2, sl.stream) != hipSuccess)
     return PMH_ERR_DEVICE;
-  S->st_batches++;
-  S->st_max_batch = std::max<uint64_t>(S->st_max_batch, nb);
+  HashArgs a = make_args(c, sl.d_ids, sl.d_w, sl.d_off, 1, sl.d_idx, sl.d_val, sl.d_id, nullptr, &sl.work);
+  a.split_log2 = sl2;
+  const int rc = enqueue_batched(c, a, &sl.work, sl.stream, S->per_cu, S->waves);
+  if (rc) return rc;
+  // then full-size passes over the pinned buffers (the GPU's first touches
+  // of their pages are slow)
+  if (out_copy(sl, 1, m) != hipSuccess ||
+      copy64(sl.dh_ids, sl.d_ids, sl.elems_cap, sl.dh_w, sl.d_w, sl.elems_cap, nullptr, nullptr, 0, sl.stream) !=
+          hipSuccess ||
+      out_copy(sl, sl.sets_cap, m) != hipSuccess || hipEventRecord(sl.ev, sl.stream) != hipSuccess ||
+      hipEventSynchronize(sl.ev) != hipSuccess)
+    return PMH_ERR_DEVICE;
   return PMH_OK;
 }
 
@@ -304,12 +390,16 @@ void fail_batch(pmh_server* S, Slot& sl, int rc) {
 
 void worker_loop(pmh_server* S) {
   (void)hipSetDevice(S->ctx->device);
+  auto us_since = [&](double t) { return (uint64_t)((now_s(S->epoch) - t) * 1e6); };
   for (;;) {
+    const double t_iter = now_s(S->epoch);
     const bool stopping = S->stop.load(std::memory_order_acquire);
     bool progressed = false;
     for (Slot& sl : S->slots) {
       if (sl.state == kFlight && hipEventQuery(sl.ev) == hipSuccess) {
+        const double t0 = now_s(S->epoch);
         finish(S, sl);
+        raise_max(S->st_max_finish_us, us_since(t0));
         progressed = true;
       }
     }
@@ -326,10 +416,13 @@ void worker_loop(pmh_server* S) {
         }
     }
     if (go) {
+      const double t0 = now_s(S->epoch);
       const int rc = launch(S, *go);
+      raise_max(S->st_max_launch_us, us_since(t0));
       if (rc) fail_batch(S, *go, rc);
       progressed = true;
     }
+    raise_max(S->st_max_iter_us, us_since(t_iter));
     if (!progressed) {
       if (stopping) {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -379,6 +472,8 @@ int pmh_server_create(pmh_ctx* c, int slots, uint64_t slot_elems, uint32_t slot_
     rc = alloc_slot_buffers(sl, elems, slot_sets, c->m);
     if (rc) break;
     rc = ensure_work(c, &sl.work, slot_sets);
+    if (rc) break;
+    rc = warm_slot(S, sl);
     if (rc) break;
   }
   if (rc) {
@@ -445,6 +540,8 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
   const uint64_t total = num ? off[num] - off[0] : 0;
   uint64_t* p_ids = nullptr;
   double* p_w = nullptr;
+  const uint64_t* src_ids = nullptr;
+  const double* src_w = nullptr;
   if (total) {
     if (hipHostMalloc(&p_ids, total * 8, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&p_w, total * 8, hipHostMallocDefault) != hipSuccess) {
@@ -453,13 +550,38 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
     }
     memcpy(p_ids, ids + off[0], total * 8);
     memcpy(p_w, w + off[0], total * 8);
+    // Device-mapped aliases for the copy kernel.  The GPU's first reads of
+    // freshly pinned pages are slow (up to ~1 ms per request) and stall the
+    // first tens of milliseconds of the replay: read the whole staging area
+    // once into a scratch buffer first, as a long-lived serving process would
+    // have done with its request buffers.
+    void* di = nullptr;
+    void* dw = nullptr;
+    const uint64_t step = 1ull << 22;
+    void* scratch = nullptr;
+    bool ok = hipHostGetDevicePointer(&di, p_ids, 0) == hipSuccess &&
+              hipHostGetDevicePointer(&dw, p_w, 0) == hipSuccess && hipMalloc(&scratch, 2 * step * 8) == hipSuccess;
+    for (uint64_t o = 0; ok && o < total; o += step) {
+      const uint64_t len = std::min<uint64_t>(step, total - o);
+      ok = copy64((const uint64_t*)di + o, scratch, len, (const uint64_t*)dw + o, (uint64_t*)scratch + step, len,
+                  nullptr, nullptr, 0, nullptr) == hipSuccess;
+    }
+    ok = ok && hipStreamSynchronize(nullptr) == hipSuccess;
+    if (scratch) (void)hipFree(scratch);
+    if (!ok) {
+      (void)hipHostFree(p_ids);
+      (void)hipHostFree(p_w);
+      return PMH_ERR_DEVICE;
+    }
+    src_ids = (const uint64_t*)di;
+    src_w = (const double*)dw;
   }
   std::vector<Request*> reqs(num);
   for (uint64_t r = 0; r < num; ++r) {
     Request* q = new Request();
     q->n = (uint32_t)(off[r + 1] - off[r]);
-    q->src_ids = p_ids + (off[r] - off[0]);
-    q->src_w = p_w + (off[r] - off[0]);
+    q->src_ids = src_ids + (off[r] - off[0]);
+    q->src_w = src_w + (off[r] - off[0]);
     q->dst_idx = out_idx ? out_idx + r * m : nullptr;
     q->dst_id = out_id ? out_id + r * m : nullptr;
     reqs[r] = q;
@@ -489,11 +611,14 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
 int pmh_server_stats(pmh_server* S, uint64_t* o) {
   if (!S || !o) return PMH_ERR_ARG;
   std::lock_guard<std::mutex> lk(S->mu);
-  o[0] = S->st_batches;
+  o[0] = S->st_batches.load(std::memory_order_relaxed);
   o[1] = S->st_done;
-  o[2] = S->st_max_batch;
+  o[2] = S->st_max_batch.load(std::memory_order_relaxed);
   o[3] = S->st_max_busy;
   o[4] = S->st_waited;
+  o[5] = S->st_max_launch_us.load(std::memory_order_relaxed);
+  o[6] = S->st_max_finish_us.load(std::memory_order_relaxed);
+  o[7] = S->st_max_iter_us.load(std::memory_order_relaxed);
   return PMH_OK;
 }
 

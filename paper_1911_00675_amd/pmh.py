@@ -328,10 +328,10 @@ class Server:
         return lat, idx, idv, wall.value
 
     def stats(self) -> dict:
-        o = np.zeros(5, dtype=np.uint64)
+        o = np.zeros(8, dtype=np.uint64)
         _check(lib().pmh_server_stats(self._s, o.ctypes.data_as(ctypes.c_void_p)), "pmh_server_stats")
         return dict(batches=int(o[0]), done=int(o[1]), max_batch=int(o[2]), max_busy_slots=int(o[3]),
-                    waited=int(o[4]))
+                    waited=int(o[4]), max_launch_us=int(o[5]), max_finish_us=int(o[6]), max_iter_us=int(o[7]))
 
     def close(self):
         if self._s:
