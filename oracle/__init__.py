@@ -10,7 +10,8 @@ Two layers:
   (Sec. 2.3-2.6) with the stop-limit tree (Sec. 2.2) and the lazy
   Fisher-Yates generator (Sec. 2.4), the interleaved ProbMinHash1a/3a
   (Sec. 2.7), a brute-force signature (eq. (1) with the hash values of
-  eq. (9)), and the random-stream primitives.
+  eq. (9)), P-MinHash (Sec. 1.1, the paper's O(nm) baseline) and the
+  random-stream primitives.
 * numpy functions below: the probability Jaccard similarity J_P written out
   from its definition (Sec. 1.1, "Incorporating Weights"), an O(N log N) form
   of it, the estimator of eq. (3), SuperMinHash's variance factor alpha(m, u)
@@ -71,6 +72,8 @@ def lib():
             "or_sign": (i32, [i32, i32, u64, u32, vp, vp, u64, vp, vp]),
             "or_decode": (None, [vp, u64, vp, vp, vp, vp]),
             "or_sign_batch": (i32, [i32, u64, u32, vp, vp, vp, u64, vp, i32, vp]),
+            "or_pminhash": (i32, [u64, u32, vp, vp, u64, vp]),
+            "or_pminhash_batch": (i32, [u64, u32, vp, vp, vp, u64, vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -202,6 +205,31 @@ def sign_batch(variant: int, seed: int, m: int, ids, weights, offsets, nthreads:
     if rc:
         raise OracleError(rc)
     return (keys, stats) if return_stats else keys
+
+
+def pminhash(seed: int, m: int, ids, weights):
+    """P-MinHash keys (uint64[m]) of one weighted set (Sec. 1.1)."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    assert ids.shape == w.shape
+    keys = np.zeros(m, dtype=np.uint64)
+    rc = lib().or_pminhash(seed & EMPTY, m, _ptr(ids), _ptr(w), ids.size, _ptr(keys))
+    if rc:
+        raise OracleError(rc)
+    return keys
+
+
+def pminhash_batch(seed: int, m: int, ids, weights, offsets, nthreads: int = 1):
+    """P-MinHash keys (uint64[num_sets, m]) of a CSR batch."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    S = off.size - 1
+    keys = np.zeros((S, m), dtype=np.uint64)
+    rc = lib().or_pminhash_batch(seed & EMPTY, m, _ptr(ids), _ptr(w), _ptr(off), S, _ptr(keys), int(nthreads))
+    if rc:
+        raise OracleError(rc)
+    return keys
 
 
 def decode(keys, ids):

@@ -732,6 +732,40 @@ int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *id
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* P-MinHash (Sec. 1.1, algorithm "P-MinHash"): every element of positive
+ * weight draws m exponential values of rate 1 scaled by its reciprocal weight,
+ * one per component, and component k keeps the smallest (eq. (2) with the
+ * hash functions of Sec. 1.1).  Reading: the k-th value of element K takes
+ * its uniform from slot 128 of point k of the element's counter stream (a
+ * slot no ProbMinHash stream uses), Exp(1) by the same stream logarithm, and
+ * the value fl(winv * Exp(1)) enters the same (value, position) key space. */
+#define O_SLOT_PMIN 128u
+static void o_pminhash(uint64_t sh, const uint64_t *ids, const double *w, uint32_t n, uint32_t m,
+                       uint64_t *keys) {
+    for (uint32_t k = 0; k < m; ++k) keys[k] = O_EMPTY;
+    for (uint32_t p = 0; p < n; ++p) {
+        if (w[p] == 0.0) continue;
+        const double winv = 1.0 / w[p];
+        const uint64_t K = o_elem_key(sh, ids[p]);
+        for (uint32_t k = 1; k <= m; ++k) {
+            const uint64_t key = o_key(winv * o_exp1(o_word(K, k, O_SLOT_PMIN)), p);
+            if (key < keys[k - 1]) keys[k - 1] = key;
+        }
+    }
+}
+
+int or_pminhash(uint64_t seed, uint32_t m, const uint64_t *ids, const double *w, uint64_t n,
+                uint64_t *keys) {
+    if ((!ids || !w) && n) return O_ERR_ARG;
+    if (m < 1 || m > O_MAX_M) return O_ERR_M_RANGE;
+    if (n > O_MAX_SET) return O_ERR_SET_TOO_LARGE;
+    int rc = o_check_weights(w, n);
+    if (rc) return rc;
+    o_pminhash(o_mix64(seed), ids, w, (uint32_t)n, m, keys);
+    return O_OK;
+}
+
 /* Decode keys into (idx, val, id): idx = position, val = truncated value,
  * id = ids[idx]; an empty component gives idx 0xFFFFFFFF, val +inf, id 0. */
 void or_decode(const uint64_t *keys, uint64_t m, const uint64_t *ids, uint32_t *idx, double *val,
@@ -755,7 +789,8 @@ void or_decode(const uint64_t *keys, uint64_t m, const uint64_t *ids, uint32_t *
 /* Batch of sets in CSR form on a pool of threads, sequential algorithm per
  * set.  keys_out: num_sets * m.  stats: {points, labels} summed. */
 typedef struct {
-    const o_params *P;
+    const o_params *P;  /* NULL: P-MinHash with m = pm */
+    uint32_t pm;
     uint64_t sh;
     const uint64_t *ids;
     const double *w;
@@ -770,7 +805,7 @@ typedef struct {
 
 static void *o_batch_worker(void *arg) {
     o_batch *B = arg;
-    const uint32_t m = B->P->m;
+    const uint32_t m = B->P ? B->P->m : B->pm;
     uint64_t *q = malloc(sizeof(uint64_t) * 2 * m);
     o_perm F;
     int rc = o_perm_init(&F, m);
@@ -780,8 +815,12 @@ static void *o_batch_worker(void *arg) {
             uint64_t s = __atomic_fetch_add(&B->next, 1, __ATOMIC_RELAXED);
             if (s >= B->num_sets) break;
             uint64_t a = B->off[s], b = B->off[s + 1];
-            o_sign_seq(B->P, B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), q, &F, &st);
-            memcpy(B->keys + s * m, q + 1, sizeof(uint64_t) * m);
+            if (B->P) {
+                o_sign_seq(B->P, B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), q, &F, &st);
+                memcpy(B->keys + s * m, q + 1, sizeof(uint64_t) * m);
+            } else {
+                o_pminhash(B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), m, B->keys + s * m);
+            }
         }
     } else {
         rc = O_ERR_OOM;
@@ -810,7 +849,7 @@ int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, c
     o_params P;
     rc = o_params_init(&P, variant, m);
     if (rc) return rc;
-    o_batch B = {&P, o_mix64(seed), ids, w, offsets, num_sets, keys_out, 0,
+    o_batch B = {&P, m, o_mix64(seed), ids, w, offsets, num_sets, keys_out, 0,
                  PTHREAD_MUTEX_INITIALIZER, 0, 0, 0};
     if (nthreads < 1) nthreads = 1;
     pthread_t *th = malloc(sizeof(pthread_t) * nthreads);
@@ -822,5 +861,29 @@ int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, c
     free(th);
     if (stats) { stats[0] = B.points; stats[1] = B.labels; }
     o_params_free(&P);
+    return B.rc;
+}
+
+/* P-MinHash over a batch of sets in CSR form (keys_out: num_sets * m). */
+int or_pminhash_batch(uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+                      const uint64_t *offsets, uint64_t num_sets, uint64_t *keys_out, int nthreads) {
+    if (!offsets || !keys_out || offsets[0] != 0) return O_ERR_ARG;
+    if (m < 1 || m > O_MAX_M) return O_ERR_M_RANGE;
+    for (uint64_t s = 0; s < num_sets; ++s) {
+        if (offsets[s + 1] < offsets[s]) return O_ERR_ARG;
+        if (offsets[s + 1] - offsets[s] > O_MAX_SET) return O_ERR_SET_TOO_LARGE;
+    }
+    int rc = o_check_weights(w, offsets[num_sets]);
+    if (rc) return rc;
+    o_batch B = {NULL, m, o_mix64(seed), ids, w, offsets, num_sets, keys_out, 0,
+                 PTHREAD_MUTEX_INITIALIZER, 0, 0, 0};
+    if (nthreads < 1) nthreads = 1;
+    pthread_t *th = malloc(sizeof(pthread_t) * nthreads);
+    int started = 0;
+    for (int t = 0; t < nthreads; ++t)
+        if (pthread_create(&th[t], NULL, o_batch_worker, &B) == 0) ++started;
+    if (started == 0) o_batch_worker(&B);
+    for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    free(th);
     return B.rc;
 }
