@@ -122,8 +122,23 @@ int pmh_hash_sets_graph(pmh_ctx* ctx, const uint64_t* ids, const double* weights
                         const uint64_t* offsets, uint64_t num_sets, uint32_t* out_idx,
                         double* out_val, uint64_t* out_id, uint64_t* out_keys, void* stream);
 
+/* P-MinHash signatures (Sec. 1.1, algorithm P-MinHash: the paper's O(n m)
+ * baseline) of num_sets weighted sets with the context's seed and m (its
+ * variant is not used): component k is the smallest key over the elements of
+ * positive weight of fl((1/w) * Exp(1)), the Exp(1) taken from word slot 128
+ * of point k of the element's counter stream with the stream logarithm.  Same
+ * inputs, outputs, keys, ties, empty-set and error conventions as
+ * pmh_hash_sets.  One ordering kernel, a persistent kernel over sets and
+ * 1,024-element chunks of sets of >= 2^11 elements (when out_keys, out_val or
+ * out_id is given to hold the merge rows), and a finishing kernel for those
+ * sets.  Timed by pmh_timing_begin like pmh_hash_sets (the persistent
+ * kernel). */
+int pmh_pminhash_sets(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                      uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
+                      uint64_t* out_keys, void* stream);
+
 /* Kernel timing for benchmarks.  After pmh_timing_begin(ctx, n) the next n
- * pmh_hash_sets calls record a HIP event pair right around their persistent
+ * pmh_hash_sets (or pmh_pminhash_sets) calls record a HIP event pair right around their persistent
  * hash kernel, on the call's stream (the ordering and split-set kernels stay
  * outside).  pmh_timing_read waits for the n pairs and writes their durations
  * in milliseconds to [host] ms[0..n); PMH_ERR_NOT_READY if fewer than n calls

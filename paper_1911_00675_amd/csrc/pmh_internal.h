@@ -104,6 +104,11 @@ hipError_t launch_hash(int variant, const HashArgs& a, int waves, int grid, size
 hipError_t launch_hash_one(int variant, const HashArgs& a, uint64_t set, int waves, size_t lds,
                            hipStream_t s);
 hipError_t occupancy(int variant, int waves, size_t lds, int* blocks_per_cu);
+// P-MinHash kernels (persistent chunk/set kernel, split-set finish)
+hipError_t launch_pmin(const HashArgs& a, int grid, hipStream_t s);
+hipError_t launch_pmin_finish(const HashArgs& a, int grid, hipStream_t s);
+hipError_t occupancy_pmin(int* blocks_per_cu);
+uint32_t pmin_split_log2();
 // A workgroup reads its set in batches of batch_size(waves) elements; its
 // chain queue holds qcap >= one batch of entries (launches size it to the LDS
 // left at the register-limited occupancy, up to 8 batches).

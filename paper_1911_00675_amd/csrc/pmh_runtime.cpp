@@ -295,6 +295,40 @@ static int check_hash_args(const pmh_ctx* c, const uint64_t* ids, const double* 
   return PMH_OK;
 }
 
+int pmh_pminhash_sets(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
+                      uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, void* stream) {
+  int rc = check_hash_args(c, ids, w, off, num_sets);
+  if (rc || num_sets == 0) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  rc = ensure_work(c, &c->work, num_sets);
+  if (rc) return rc;
+  HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
+  a.split_log2 = a.big_keys ? pmin_split_log2() : 0u;
+  hipStream_t s = (hipStream_t)stream;
+  int per_cu = 0;
+  if (occupancy_pmin(&per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+  const uint64_t items = a.split_log2 ? num_sets << (21 - a.split_log2) : num_sets;
+  const uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cu * (uint64_t)per_cu, items);
+  const WorkArgs wa = c->work.args();
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->tnext < c->tcount) {
+    ev0 = c->tev[2 * c->tnext];
+    ev1 = c->tev[2 * c->tnext + 1];
+    c->tnext++;
+  }
+  if (launch_order(a.off, num_sets, a.split_log2, wa, c->status, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (a.split_log2 && launch_big_init(wa, a.m, a.big_keys, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (launch_pmin(a, (int)grid, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return PMH_ERR_DEVICE;
+  if (a.split_log2) {
+    const uint64_t fgrid = std::min<uint64_t>((uint64_t)c->num_cu * (uint64_t)per_cu, num_sets);
+    if (launch_pmin_finish(a, (int)fgrid, s) != hipSuccess) return PMH_ERR_DEVICE;
+  }
+  return PMH_OK;
+}
+
 int pmh_hash_sets(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
                   uint32_t* idx, double* val, uint64_t* id, uint64_t* keys, void* stream) {
   int rc = check_hash_args(c, ids, w, off, num_sets);

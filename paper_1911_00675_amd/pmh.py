@@ -32,6 +32,7 @@ SIGNATURES = {
     "pmh_max_m": (_u32, [_i32]),
     "pmh_status_str": (ctypes.c_char_p, [_i32]),
     "pmh_hash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
+    "pmh_pminhash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_graph": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_get_status": (_i32, [_vp, _vp]),
@@ -165,14 +166,16 @@ class Context:
     def hash_sets(self, ids, weights, offsets, out: Signatures | None = None, mode: str = "batched",
                   stream=None, outputs=("idx", "val", "id", "keys")) -> Signatures:
         """Signatures of a CSR batch of device tensors (ids int64/uint64,
-        weights float64, offsets int64/uint64 with num_sets+1 entries)."""
+        weights float64, offsets int64/uint64 with num_sets+1 entries).
+        mode: "batched", "plain", "graph" (ProbMinHash of the context's
+        variant) or "pminhash" (P-MinHash with the context's seed and m)."""
         torch = _torch()
         num_sets = int(offsets.numel()) - 1
         if out is None:
             out = self.alloc_outputs(num_sets, outputs)
         i64 = (torch.int64, torch.uint64)
         fn = {"batched": lib().pmh_hash_sets, "plain": lib().pmh_hash_sets_plain,
-              "graph": lib().pmh_hash_sets_graph}[mode]
+              "graph": lib().pmh_hash_sets_graph, "pminhash": lib().pmh_pminhash_sets}[mode]
         rc = fn(self._c, _dptr(ids, i64, "ids"), _dptr(weights, (torch.float64,), "weights"),
                 _dptr(offsets, i64, "offsets"), num_sets,
                 _dptr(out.idx, (torch.int32,), "idx"), _dptr(out.val, (torch.float64,), "val"),

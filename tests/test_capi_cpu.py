@@ -55,6 +55,7 @@ def test_argument_errors_without_device(lib):
     assert lib.pmh_init(1, 1, 3, ctypes.byref(out)) == 3        # m = 1 with PMH3
     assert lib.pmh_init(1, 8, 5, ctypes.byref(out)) == 1        # bad variant
     assert lib.pmh_hash_sets(None, None, None, None, 1, None, None, None, None, None) == 1
+    assert lib.pmh_pminhash_sets(None, None, None, None, 1, None, None, None, None, None) == 1
     assert lib.pmh_estimate(None, None, None, None, 4, None) == 1
 
 
