@@ -36,6 +36,12 @@ VARIANTS = (1, 3)
 # truncated-exponential fast path).
 OPS_PER_ELEMENT = {1: 32 + 62, 3: 32 + 33}
 OPS_PER_POINT = {1: 62, 3: 33}
+# P-MinHash: VALU instructions per (element, component) pair in its inner loop
+# (word hash, Exp(1) by the stream logarithm, scaling, key, running minimum),
+# counted in the compiled gfx950 ISA of k_pmin.
+OPS_PER_PMIN_PAIR = 48
+BREAK_EVEN_N = (1, 2, 5, 10, 20, 50, 100, 200, 500, 1000)
+BREAK_EVEN_SETS = 2000
 PEAK_VALU = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 PEAK_HBM = 8.0e12                     # bytes/s
 
@@ -88,6 +94,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-break-even", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--cpu-sets", type=int, default=3000)
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
@@ -107,7 +114,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
-        args.no_plain = args.no_serving = args.no_cpu = True
+        args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = True
     import torch
     from paper_1911_00675_amd import pmh, workloads as W
 
@@ -221,6 +228,58 @@ def main():
                    "server": st}
         log(f"serving: {latency}")
 
+    # ------------------------------------------- P-MinHash break-even study
+    # Sec. 4 compares the ProbMinHash variants with P-MinHash over the set
+    # size n: batches of BREAK_EVEN_SETS sets of n elements (Exp(1) weights),
+    # m = M, one whole call each (ordering, kernels, finishing).
+    break_even = None
+    if not args.no_break_even:
+        bctx = {v: pmh.Context(SEED, M, v) for v in (1, 2, 3, 4)}
+        times = {k: [] for k in ("pminhash", "pmh1", "pmh2", "pmh3", "pmh4")}
+        pmin_kernel_ms = None
+        for n in BREAK_EVEN_N:
+            bb = W.random_sets(n, BREAK_EVEN_SETS, n, n, "exp")
+            bi, bw, bo = pmh.to_device(bb.ids), pmh.to_device(bb.weights), pmh.to_device(bb.offsets)
+            bout = bctx[1].alloc_outputs(BREAK_EVEN_SETS, ("idx", "id"))
+            for name, ctx, mode in [("pminhash", bctx[1], "pminhash")] + [(f"pmh{v}", bctx[v], "batched")
+                                                                            for v in (1, 2, 3, 4)]:
+                ctx.hash_sets(bi, bw, bo, out=bout, mode=mode)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                if name == "pminhash" and n == BREAK_EVEN_N[-1]:
+                    ctx.timing_begin(3)
+                e0.record(stream)
+                for _ in range(3):
+                    ctx.hash_sets(bi, bw, bo, out=bout, mode=mode)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times[name].append(e0.elapsed_time(e1) / 3)
+                if name == "pminhash" and n == BREAK_EVEN_N[-1]:
+                    pmin_kernel_ms = float(np.mean(ctx.timing_read(3)))
+                if ctx.status() != pmh.PMH_OK:
+                    raise RuntimeError(f"break-even {name} n={n}: status {ctx.status()}")
+        for ctx in bctx.values():
+            ctx.close()
+        def break_even_n(tp, tv):
+            """Smallest n from which the variant is faster at every larger n."""
+            for i in range(len(BREAK_EVEN_N)):
+                if all(tv[j] < tp[j] for j in range(i, len(BREAK_EVEN_N))):
+                    return BREAK_EVEN_N[i]
+            return None
+        be = {f"pmh{v}": break_even_n(times["pminhash"], times[f"pmh{v}"]) for v in (1, 2, 3, 4)}
+        pairs = BREAK_EVEN_SETS * BREAK_EVEN_N[-1] * M
+        pmin_ops = pairs * OPS_PER_PMIN_PAIR / (pmin_kernel_ms * 1e-3)
+        break_even = {
+            "m": M, "sets_per_call": BREAK_EVEN_SETS, "n": list(BREAK_EVEN_N), "weights": "Exp(1)",
+            "ms_per_call": times,
+            "break_even_n": be,
+            "pminhash_roofline": {"bound": "alu", "kernel": "k_pmin", "n": BREAK_EVEN_N[-1],
+                                  "achieved": pmin_ops / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
+                                  "frac": pmin_ops / PEAK_VALU, "launch_ms": pmin_kernel_ms,
+                                  "ops_model": {"per_pair": OPS_PER_PMIN_PAIR, "pairs": pairs}},
+        }
+        log(f"break-even: {break_even}")
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -256,6 +315,7 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "latency": latency,
+        "break_even": break_even,
     }
     print(json.dumps(out))
 
