@@ -10,8 +10,8 @@ Two layers:
   (Sec. 2.3-2.6) with the stop-limit tree (Sec. 2.2) and the lazy
   Fisher-Yates generator (Sec. 2.4), the interleaved ProbMinHash1a/3a
   (Sec. 2.7), a brute-force signature (eq. (1) with the hash values of
-  eq. (9)), P-MinHash (Sec. 1.1, the paper's O(nm) baseline) and the
-  random-stream primitives.
+  eq. (9)), P-MinHash (Sec. 1.1, the paper's O(nm) baseline), the b-bit
+  reduction of Sec. 1.3 and the random-stream primitives.
 * numpy functions below: the probability Jaccard similarity J_P written out
   from its definition (Sec. 1.1, "Incorporating Weights"), an O(N log N) form
   of it, the estimator of eq. (3), SuperMinHash's variance factor alpha(m, u)
@@ -73,6 +73,9 @@ def lib():
             "or_decode": (None, [vp, u64, vp, vp, vp, vp]),
             "or_sign_batch": (i32, [i32, u64, u32, vp, vp, vp, u64, vp, i32, vp]),
             "or_pminhash": (i32, [u64, u32, vp, vp, u64, vp]),
+            "or_bbit_hash": (u64, [u64, u64]),
+            "or_bbit_pack": (i32, [vp, u64, u32, u32, vp]),
+            "or_bbit_equal": (u32, [vp, vp, u32, u32]),
             "or_pminhash_batch": (i32, [u64, u32, vp, vp, vp, u64, vp, i32]),
         }
         for name, (res, args) in sig.items():
@@ -230,6 +233,36 @@ def pminhash_batch(seed: int, m: int, ids, weights, offsets, nthreads: int = 1):
     if rc:
         raise OracleError(rc)
     return keys
+
+
+def bbit_words(m: int, b: int) -> int:
+    return (m * b + 63) // 64
+
+
+def bbit_pack(ids, m: int, b: int):
+    """b-bit reduction (Sec. 1.3) of signatures given by their element ids
+    (uint64[num_sigs, m]; 0 = empty), packed into uint64[num_sigs, words]."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64).reshape(-1, m)
+    out = np.zeros((ids.shape[0], bbit_words(m, b)), dtype=np.uint64)
+    rc = lib().or_bbit_pack(_ptr(ids), ids.shape[0], m, b, _ptr(out))
+    if rc:
+        raise OracleError(rc)
+    return out
+
+
+def bbit_equal(a, c, m: int, b: int) -> int:
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    c = np.ascontiguousarray(c, dtype=np.uint64)
+    return int(lib().or_bbit_equal(_ptr(a), _ptr(c), m, b))
+
+
+def bbit_estimate(equal: int, m: int, b: int) -> float:
+    """J estimate from b-bit signatures: components of different elements
+    agree with probability 2^-b, so E[equal/m] = J + (1 - J) 2^-b and
+    (equal/m - 2^-b) / (1 - 2^-b) is unbiased (the bias Sec. 1.3 says must be
+    accounted for)."""
+    r = 2.0 ** -b
+    return (equal / m - r) / (1.0 - r)
 
 
 def decode(keys, ids):

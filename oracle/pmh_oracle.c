@@ -766,6 +766,44 @@ int or_pminhash(uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
     return O_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* b-bit reduction (Sec. 1.3, algorithm "Reduction to a b-bit signature"):
+ * component k (1-based) of value z -- the component's element id, 0 when the
+ * component is empty -- becomes the b least significant bits of a hash of
+ * the pair (z, k).  Reading: hash = mix64(mix64(z) + k*phi), so equal ids in
+ * the same component always agree and different ids agree with probability
+ * 2^-b, independently across components.  Packing: b in {1, 2, 4, 8, 16},
+ * component k-1 in bits [((k-1) b) mod 64, +b) of word ((k-1) b) / 64,
+ * ceil(m b / 64) words per signature, unused high bits zero. */
+uint64_t or_bbit_hash(uint64_t z, uint64_t k) { return o_mix64(o_mix64(z) + k * O_PHI); }
+
+int or_bbit_pack(const uint64_t *ids, uint64_t num_sigs, uint32_t m, uint32_t b, uint64_t *out) {
+    if (m < 1 || (b != 1 && b != 2 && b != 4 && b != 8 && b != 16)) return O_ERR_ARG;
+    const uint64_t W = ((uint64_t)m * b + 63) / 64;
+    const uint64_t mask = ((uint64_t)1 << b) - 1;
+    for (uint64_t s = 0; s < num_sigs; ++s) {
+        uint64_t *o = out + s * W;
+        for (uint64_t w = 0; w < W; ++w) o[w] = 0;
+        for (uint32_t k = 0; k < m; ++k) {
+            const uint64_t v = or_bbit_hash(ids[s * m + k], (uint64_t)k + 1) & mask;
+            const uint64_t bit = (uint64_t)k * b;
+            o[bit / 64] |= v << (bit % 64);
+        }
+    }
+    return O_OK;
+}
+
+/* Number of components whose b-bit fields agree, by unpacking. */
+uint32_t or_bbit_equal(const uint64_t *a, const uint64_t *c, uint32_t m, uint32_t b) {
+    const uint64_t mask = ((uint64_t)1 << b) - 1;
+    uint32_t eq = 0;
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint64_t bit = (uint64_t)k * b;
+        eq += ((a[bit / 64] >> (bit % 64)) & mask) == ((c[bit / 64] >> (bit % 64)) & mask);
+    }
+    return eq;
+}
+
 /* Decode keys into (idx, val, id): idx = position, val = truncated value,
  * id = ids[idx]; an empty component gives idx 0xFFFFFFFF, val +inf, id 0. */
 void or_decode(const uint64_t *keys, uint64_t m, const uint64_t *ids, uint32_t *idx, double *val,
