@@ -176,6 +176,20 @@ int pmh_estimate_pairs(const uint64_t* idA, const uint32_t* idxA, const uint64_t
  * counts[k][k] uint16 [device], saturating at 65535. */
 int pmh_allpairs_counts(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts, void* stream);
 
+/* b-bit reduction (Sec. 1.3, algorithm "Reduction to a b-bit signature") of
+ * num_sigs signatures given by their element ids id[num_sigs][m] [device]
+ * (the out_id output; 0 = empty component): component k (1-based) keeps the
+ * b low bits of mix64(mix64(id) + k * 0x9E3779B97F4A7C15), b in {1, 2, 4, 8,
+ * 16}; packed into out[num_sigs][ceil(m b / 64)] uint64 [device], component
+ * k-1 at bit (k-1) b of the signature's bit string, padding bits zero.
+ * Different elements agree in a component with probability 2^-b, so
+ * (equal/m - 2^-b) / (1 - 2^-b) estimates J_P.  1 <= m <= 16384. */
+int pmh_bbit_pack(const uint64_t* id, uint64_t num_sigs, uint32_t m, uint32_t b, uint64_t* out, void* stream);
+
+/* All-pairs equal-field counts of k packed b-bit signatures sig[k][ceil(m b
+ * / 64)] [device]: counts[k][k] uint16 [device]. */
+int pmh_bbit_allpairs(const uint64_t* sig, uint32_t k, uint32_t m, uint32_t b, uint16_t* counts, void* stream);
+
 /* Copy a constant table to [host] out (count doubles).  which: 0 beta (PMH2,
  * m+1), 1 lambda_i, 2 c1_i, 3 c2_i, 4 c3_i, 5 gamma_i, 6 dgamma_i (PMH4, m
  * each), 7 scalars {lambda, c1, c2, c3, delta, 0, 0, 0} (8), 8 expm1

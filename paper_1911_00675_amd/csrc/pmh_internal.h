@@ -121,6 +121,10 @@ hipError_t launch_estimate(const uint64_t* idA, const uint32_t* idxA, const uint
                            hipStream_t s);
 hipError_t launch_allpairs(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts,
                            hipStream_t s);
+hipError_t launch_bbit_pack(const uint64_t* id, uint64_t num_sigs, uint32_t m, uint32_t b, uint64_t* out,
+                            hipStream_t s);
+hipError_t launch_bbit_allpairs(const uint64_t* sig, uint32_t k, uint32_t m, uint32_t b, uint16_t* counts,
+                                hipStream_t s);
 hipError_t launch_debug_eval(int what, const double* in, const uint64_t* in_u, double* out,
                              uint64_t* out_u, uint64_t n, uint32_t m, int variant, Tables t,
                              hipStream_t s);

@@ -1470,6 +1470,84 @@ __global__ __launch_bounds__(256) void k_allpairs(const uint32_t* fp, uint32_t k
     }
 }
 
+// ----------------------------------------------------- b-bit reduction
+// Sec. 1.3, algorithm "Reduction to a b-bit signature": component k (1-based)
+// of element id z (0 = empty) keeps the b low bits of mix64(mix64(z) + k phi);
+// fields are packed b in {1, 2, 4, 8, 16} per 64-bit word (component k-1 at
+// bit (k-1) b of the signature's bit string), ceil(m b / 64) words per
+// signature, high padding bits zero.  One thread per output word.
+__global__ __launch_bounds__(256) void k_bbit_pack(const uint64_t* id, uint64_t num_sigs, uint32_t m, uint32_t b,
+                                                   uint64_t* out) {
+  const uint64_t W = ((uint64_t)m * b + 63) / 64;
+  const uint64_t word = blockIdx.x * 256ull + threadIdx.x;
+  if (word >= num_sigs * W) return;
+  const uint64_t s = word / W, w = word % W;
+  const uint32_t per = 64u / b;
+  const uint32_t k0 = (uint32_t)w * per, k1 = k0 + per < m ? k0 + per : m;
+  const uint64_t mask = (1ull << b) - 1ull;
+  const uint64_t* z = id + s * m;
+  uint64_t acc = 0;
+  for (uint32_t k = k0; k < k1; ++k)
+    acc |= (mix64(mix64(z[k]) + (uint64_t)(k + 1) * kPhi) & mask) << ((k - k0) * b);
+  out[word] = acc;
+}
+
+// Fields of x that are nonzero, one bit each (at the field's lowest bit).
+template <int B>
+__device__ __forceinline__ uint64_t bbit_nonzero(uint64_t x) {
+  if constexpr (B >= 2) x |= x >> 1;
+  if constexpr (B >= 4) x |= x >> 2;
+  if constexpr (B >= 8) x |= x >> 4;
+  if constexpr (B >= 16) x |= x >> 8;
+  constexpr uint64_t low = B == 1 ? ~0ull : B == 2 ? 0x5555555555555555ull : B == 4 ? 0x1111111111111111ull
+                                  : B == 8 ? 0x0101010101010101ull : 0x0001000100010001ull;
+  return x & low;
+}
+
+// All-pairs equal-field counts of k packed b-bit signatures (W words each):
+// 64x64 signature tiles, kApK words staged in LDS, 4x4 pairs per thread;
+// equal = m - (fields that differ), padding fields being zero in both.
+template <int B>
+__global__ __launch_bounds__(256) void k_bbit_allpairs(const uint64_t* sig, uint32_t k, uint32_t W, uint32_t m,
+                                                       uint16_t* counts) {
+  __shared__ uint64_t sa[kApK][kApTile + 1];
+  __shared__ uint64_t sb[kApK][kApTile + 1];
+  const uint32_t bi = blockIdx.y * kApTile, bj = blockIdx.x * kApTile;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  uint32_t diff[4][4] = {};
+  for (uint32_t c0 = 0; c0 < W; c0 += kApK) {
+    for (int e = threadIdx.x; e < kApK * kApTile; e += 256) {
+      const int r = e / kApK, c = e % kApK;
+      const uint32_t cc = c0 + c;
+      sa[c][r] = (bi + r < k && cc < W) ? sig[(uint64_t)(bi + r) * W + cc] : 0ull;
+      sb[c][r] = (bj + r < k && cc < W) ? sig[(uint64_t)(bj + r) * W + cc] : 0ull;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < kApK; ++c) {
+      uint64_t av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = sa[c][ty * 4 + u];
+        bv[u] = sb[c][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) diff[u][v] += (uint32_t)__popcll(bbit_nonzero<B>(av[u] ^ bv[v]));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t r = bi + ty * 4 + u, c = bj + tx * 4 + v;
+      const uint32_t eq = m - diff[u][v];
+      if (r < k && c < k) counts[(uint64_t)r * k + c] = (uint16_t)(eq > 65535u ? 65535u : eq);
+    }
+}
+
 // --------------------------------------------------------- debug primitives
 // what: 0 log(x), 1 log1p(x), 2 expm1(x), 3 Exp(1) of word u, 4 mix64(u),
 // 5 truncated exponential of (K = u, point k+1) with PMH3 constants,
@@ -1641,6 +1719,31 @@ hipError_t launch_allpairs(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t*
   if (k == 0) return hipSuccess;
   const uint32_t tiles = (k + kApTile - 1) / kApTile;
   hipLaunchKernelGGL(k_allpairs, dim3(tiles, tiles), dim3(256), 0, s, fp, k, m, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_bbit_pack(const uint64_t* id, uint64_t num_sigs, uint32_t m, uint32_t b, uint64_t* out,
+                            hipStream_t s) {
+  const uint64_t words = num_sigs * (((uint64_t)m * b + 63) / 64);
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bbit_pack, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, s, id, num_sigs, m, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bbit_allpairs(const uint64_t* sig, uint32_t k, uint32_t m, uint32_t b, uint16_t* counts,
+                                hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  const uint32_t W = (uint32_t)(((uint64_t)m * b + 63) / 64);
+  const uint32_t tiles = (k + kApTile - 1) / kApTile;
+  const dim3 g(tiles, tiles);
+  switch (b) {
+    case 1: hipLaunchKernelGGL(k_bbit_allpairs<1>, g, dim3(256), 0, s, sig, k, W, m, counts); break;
+    case 2: hipLaunchKernelGGL(k_bbit_allpairs<2>, g, dim3(256), 0, s, sig, k, W, m, counts); break;
+    case 4: hipLaunchKernelGGL(k_bbit_allpairs<4>, g, dim3(256), 0, s, sig, k, W, m, counts); break;
+    case 8: hipLaunchKernelGGL(k_bbit_allpairs<8>, g, dim3(256), 0, s, sig, k, W, m, counts); break;
+    case 16: hipLaunchKernelGGL(k_bbit_allpairs<16>, g, dim3(256), 0, s, sig, k, W, m, counts); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

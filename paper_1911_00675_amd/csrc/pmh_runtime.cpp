@@ -501,6 +501,20 @@ int pmh_allpairs_counts(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* co
   return launch_allpairs(fp, k, m, counts, (hipStream_t)stream) == hipSuccess ? PMH_OK : PMH_ERR_DEVICE;
 }
 
+static bool bbit_ok(uint32_t b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16; }
+
+int pmh_bbit_pack(const uint64_t* id, uint64_t num_sigs, uint32_t m, uint32_t b, uint64_t* out, void* stream) {
+  if (num_sigs == 0) return PMH_OK;
+  if (!id || !out || m == 0 || m > kMaxM || !bbit_ok(b)) return PMH_ERR_ARG;
+  return launch_bbit_pack(id, num_sigs, m, b, out, (hipStream_t)stream) == hipSuccess ? PMH_OK : PMH_ERR_DEVICE;
+}
+
+int pmh_bbit_allpairs(const uint64_t* sig, uint32_t k, uint32_t m, uint32_t b, uint16_t* counts, void* stream) {
+  if (k == 0) return PMH_OK;
+  if (!sig || !counts || m == 0 || m > kMaxM || !bbit_ok(b)) return PMH_ERR_ARG;
+  return launch_bbit_allpairs(sig, k, m, b, counts, (hipStream_t)stream) == hipSuccess ? PMH_OK : PMH_ERR_DEVICE;
+}
+
 int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
   if (!c || !out) return PMH_ERR_ARG;
   DeviceGuard g(c->device);

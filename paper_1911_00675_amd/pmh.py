@@ -33,6 +33,8 @@ SIGNATURES = {
     "pmh_status_str": (ctypes.c_char_p, [_i32]),
     "pmh_hash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_pminhash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
+    "pmh_bbit_pack": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp]),
+    "pmh_bbit_allpairs": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp]),
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_graph": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_get_status": (_i32, [_vp, _vp]),
@@ -277,6 +279,30 @@ def allpairs_counts(fp, stream=None):
     rc = lib().pmh_allpairs_counts(_dptr(fp, (torch.int32,), "fp"), k, m, _dptr(counts, (torch.int16,), "counts"),
                                    _stream_ptr(stream))
     _check(rc, "pmh_allpairs_counts")
+    return counts
+
+
+def bbit_pack(ids, b: int, stream=None):
+    """b-bit reduction (Sec. 1.3) of signatures given by their element ids
+    [num_sigs, m] (int64 device tensor, 0 = empty): int64 [num_sigs, words]."""
+    torch = _torch()
+    S, m = ids.shape
+    out = torch.empty((S, (m * b + 63) // 64), dtype=torch.int64, device="cuda")
+    rc = lib().pmh_bbit_pack(_dptr(ids, (torch.int64, torch.uint64), "ids"), S, m, b,
+                             _dptr(out, (torch.int64,), "out"), _stream_ptr(stream))
+    _check(rc, "pmh_bbit_pack")
+    return out
+
+
+def bbit_allpairs(sig, m: int, b: int, stream=None):
+    """All-pairs equal-field counts of packed b-bit signatures [k, words]:
+    int16 [k, k] (bits of uint16)."""
+    torch = _torch()
+    k = sig.shape[0]
+    counts = torch.empty((k, k), dtype=torch.int16, device="cuda")
+    rc = lib().pmh_bbit_allpairs(_dptr(sig, (torch.int64,), "sig"), k, m, b, _dptr(counts, (torch.int16,), "counts"),
+                                 _stream_ptr(stream))
+    _check(rc, "pmh_bbit_allpairs")
     return counts
 
 
