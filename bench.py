@@ -95,6 +95,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-break-even", action="store_true")
+    ap.add_argument("--no-allpairs", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--cpu-sets", type=int, default=3000)
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
@@ -114,7 +115,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
-        args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = True
+        args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = args.no_allpairs = True
     import torch
     from paper_1911_00675_amd import pmh, workloads as W
 
@@ -280,6 +281,41 @@ def main():
         }
         log(f"break-even: {break_even}")
 
+    # -------------------------------------------------- all-pairs estimation
+    # Eq. (3) over every pair of 20,000 signatures of m = 4096 components
+    # (2e8 pairs): 32-bit fingerprints of the element ids, and the b-bit
+    # reductions of Sec. 1.3 (packed, b = 1 and 4).  Random ids stand in for
+    # signatures: the kernels' work does not depend on the values.
+    allpairs = None
+    if not args.no_allpairs:
+        ka, ma = 20_000, 4096
+        rng = np.random.default_rng(SEED)
+        aid = torch.from_numpy(rng.integers(1, 2**62, size=(ka, ma), dtype=np.int64)).cuda()
+        afp = (aid & 0xFFFFFFFF).to(torch.int32)
+
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        allpairs = {"signatures": ka, "m": ma, "pairs": ka * ka,
+                    "fp32_ms": timed(lambda: pmh.allpairs_counts(afp))}
+        for bb in (1, 4):
+            packed = pmh.bbit_pack(aid, bb)
+            allpairs[f"b{bb}_pack_ms"] = timed(lambda: pmh.bbit_pack(aid, bb))
+            allpairs[f"b{bb}_ms"] = timed(lambda: pmh.bbit_allpairs(packed, ma, bb))
+        allpairs["component_compares_per_s"] = {
+            k.replace("_ms", ""): ka * ka * ma / (v * 1e-3) for k, v in allpairs.items()
+            if k.endswith("_ms") and "pack" not in k}
+        del aid, afp
+        log(f"allpairs: {allpairs}")
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -316,6 +352,7 @@ def main():
         "plain": plain,
         "latency": latency,
         "break_even": break_even,
+        "allpairs": allpairs,
     }
     print(json.dumps(out))
 
