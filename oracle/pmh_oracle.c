@@ -266,6 +266,7 @@ typedef struct {
     double *lam4, *c14, *c24, *c34; /* PMH4, i = 1..m-1 */
     double *gam, *dgam;             /* PMH4: gamma[0..m-1], dgamma[1..m-1] */
     double delta;                   /* PMH4 */
+    int binary;                     /* Sec. 2.9 specialisation (variants 5..8 = binary 1..4) */
 } o_params;
 
 static unsigned o_bitlen(uint32_t m) {
@@ -284,6 +285,14 @@ static void o_params_free(o_params *P) {
 
 static int o_params_init(o_params *P, int variant, uint32_t m) {
     memset(P, 0, sizeof(*P));
+    /* Variants 5..8: ProbMinHash1..4 specialised to binary weights (Sec. 2.9,
+     * "Conventional Jaccard Similarity"), called with unit weights.  PMH1/2
+     * are unchanged (1/w = 1); PMH3 draws U[0,1) instead of the truncated
+     * exponential; PMH4 takes gamma_i = i and U[0,1) for both samplers. */
+    if (variant >= 5 && variant <= 8) {
+        P->binary = 1;
+        variant -= 4;
+    }
     if (variant < 1 || variant > 4) return O_ERR_ARG;
     if (m < 1 || m > O_MAX_M) return O_ERR_M_RANGE;
     if ((variant == 3 || variant == 4) && m < 2) return O_ERR_VARIANT_M;
@@ -328,6 +337,8 @@ static int o_params_init(o_params *P, int variant, uint32_t m) {
         for (uint32_t i = 1; i < m; ++i)
             P->gam[i] = or_log1p((double)i / (double)(m - i)) / P->lam4[1];
         P->dgam[0] = 0.0;
+        if (P->binary)
+            for (uint32_t i = 0; i < m; ++i) P->gam[i] = (double)i;
         for (uint32_t i = 1; i < m; ++i) P->dgam[i] = P->gam[i] - P->gam[i - 1];
         P->delta = 1.0 / P->lam4[1];
     }
@@ -346,11 +357,13 @@ static inline uint64_t o_spacing(const o_params *P, uint64_t K, uint64_t i) {
 static inline double o_fixed_value(double winv, uint64_t T) { return winv * ((double)T * 0x1p-32); }
 
 static inline double o_value3(const o_params *P, uint64_t K, uint64_t i, double winv) {
+    if (P->binary) return (double)(i - 1) + o_u32(o_word(K, i, O_SLOT_POINT));
     double lb = winv * (double)(i - 1);
     return lb + winv * o_te(K, i, P->lam3, P->c1, P->c2, P->c3);
 }
 static inline double o_value4(const o_params *P, uint64_t K, uint64_t i, double winv) {
     uint32_t m = P->m;
+    if (P->binary) return (double)(i - 1) + o_u32(o_word(K, i, O_SLOT_POINT));
     if (i < m)
         return winv * (P->gam[i - 1] +
                        P->dgam[i] * o_te(K, i, P->lam4[i], P->c14[i], P->c24[i], P->c34[i]));
@@ -661,9 +674,9 @@ int or_constants(int variant, uint32_t m, uint32_t i, double *out) {
     o_params P;
     int rc = o_params_init(&P, variant, m);
     if (rc) return rc;
-    if (variant == 2 && i >= 1 && i <= m) out[0] = P.beta[i];
-    if (variant == 3) { out[0] = P.lam3; out[1] = P.c1; out[2] = P.c2; out[3] = P.c3; }
-    if (variant == 4 && i < m) {
+    if (P.variant == 2 && i >= 1 && i <= m) out[0] = P.beta[i];
+    if (P.variant == 3) { out[0] = P.lam3; out[1] = P.c1; out[2] = P.c2; out[3] = P.c3; }
+    if (P.variant == 4 && i < m) {
         out[0] = P.lam4[i]; out[1] = P.c14[i]; out[2] = P.c24[i]; out[3] = P.c34[i];
         out[4] = P.gam[i]; out[5] = P.dgam[i]; out[6] = P.delta;
     }
@@ -683,17 +696,17 @@ int or_stream(int variant, uint32_t m, uint64_t K, double winv, uint64_t count, 
     if (o_perm_init(&F, m) != O_OK) { o_perm_free(&F); o_params_free(&P); return O_ERR_OOM; }
     o_perm_reset(&F);
     uint64_t T = 0;
-    uint64_t last = (variant == 2 || variant == 4) ? m : P.imax;
+    uint64_t last = (P.variant == 2 || P.variant == 4) ? m : P.imax;
     for (uint64_t i = 1; i <= count && i <= last; ++i) {
-        if (variant <= 2) {
+        if (P.variant <= 2) {
             T += o_spacing(&P, K, i);
             xs[i - 1] = o_fixed_value(winv, T);
-        } else if (variant == 3) {
+        } else if (P.variant == 3) {
             xs[i - 1] = o_value3(&P, K, i, winv);
         } else {
             xs[i - 1] = o_value4(&P, K, i, winv);
         }
-        ls[i - 1] = (variant == 1 || variant == 3) ? o_lemire(K, i, m) : o_perm_next(&F, K);
+        ls[i - 1] = (P.variant == 1 || P.variant == 3) ? o_lemire(K, i, m) : o_perm_next(&F, K);
     }
     o_perm_free(&F);
     o_params_free(&P);
@@ -711,7 +724,7 @@ int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *id
     o_params P;
     rc = o_params_init(&P, variant, m);
     if (rc) return rc;
-    if (mode == 1 && variant != 1 && variant != 3) { o_params_free(&P); return O_ERR_ARG; }
+    if (mode == 1 && P.variant != 1 && P.variant != 3) { o_params_free(&P); return O_ERR_ARG; }
     uint64_t sh = o_mix64(seed);
     o_stats st = {0, 0};
     if (mode == 2) {
