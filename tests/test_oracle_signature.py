@@ -102,8 +102,9 @@ def test_argument_errors(oracle):
         with pytest.raises(oracle.OracleError) as e:
             oracle.sign(1, 0, m, ids, np.array([1.0, 1.0]))
         assert e.value.code == oracle.ERR_M_RANGE
-    with pytest.raises(oracle.OracleError):
-        oracle.sign(5, 0, 8, ids, np.array([1.0, 1.0]))
+    for bad_variant in (0, 9):  # 5..8 are the binary specialisations
+        with pytest.raises(oracle.OracleError):
+            oracle.sign(bad_variant, 0, 8, ids, np.array([1.0, 1.0]))
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4])
