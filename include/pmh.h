@@ -137,9 +137,22 @@ int pmh_pminhash_sets(pmh_ctx* ctx, const uint64_t* ids, const double* weights, 
                       uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
                       uint64_t* out_keys, void* stream);
 
+/* Signatures of num_sets plain sets (every element weight 1, no weight array):
+ * the binary specialisations of Sec. 2.9.  ProbMinHash1/2 give exactly what
+ * pmh_hash_sets gives with unit weights.  ProbMinHash3 draws point i of an
+ * element as (i - 1) + U with U uniform in [0,1) (no truncated exponential),
+ * and ProbMinHash4 takes gamma_i = i with the same U for its points, which
+ * makes it SuperMinHash.  U is the high 32 bits of the point's stream word
+ * times 2^-32.  ids, offsets [device]; outputs [device] or NULL; same keys,
+ * ties, empty-set, split and error conventions as pmh_hash_sets (no weight
+ * can be invalid).  Timed by pmh_timing_begin like pmh_hash_sets. */
+int pmh_hash_sets_binary(pmh_ctx* ctx, const uint64_t* ids, const uint64_t* offsets, uint64_t num_sets,
+                         uint32_t* out_idx, double* out_val, uint64_t* out_id, uint64_t* out_keys,
+                         void* stream);
+
 /* Kernel timing for benchmarks.  After pmh_timing_begin(ctx, n) the next n
- * pmh_hash_sets (or pmh_pminhash_sets) calls record a HIP event pair right around their persistent
- * hash kernel, on the call's stream (the ordering and split-set kernels stay
+ * pmh_hash_sets (pmh_hash_sets_binary, pmh_pminhash_sets) calls record a HIP
+ * event pair right around their persistent hash kernel, on the call's stream (the ordering and split-set kernels stay
  * outside).  pmh_timing_read waits for the n pairs and writes their durations
  * in milliseconds to [host] ms[0..n); PMH_ERR_NOT_READY if fewer than n calls
  * were recorded.  The events are owned by the context. */

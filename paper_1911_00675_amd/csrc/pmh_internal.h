@@ -72,6 +72,7 @@ struct HashArgs {
   double c0, grow, chain_expect, mini_expect;
   int max_rounds, lane_budget, kmax_refresh;
   uint32_t qcap;             // chain queue entries in LDS (>= one batch)
+  uint32_t binary;           // binary weights: no weight array, every weight 1 (Sec. 2.9 values for PMH3/4)
   uint32_t* status;          // device status word
   const uint32_t* order;     // work list (set indices), heavy first
   uint32_t* counter;         // work counters (zeroed by the order kernel)

@@ -39,11 +39,12 @@ namespace {
 constexpr double kLn2Hi = 0x1.62e42fefa0000p-1;  // ln 2 rounded to 36 bits
 constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
 // Lane-mode Fisher-Yates steps kept in registers: ProbMinHash2 16 (3 waves
-// per SIMD), ProbMinHash4 6 (its per-step constants leave room for no more at
-// 3 waves per SIMD).  Measured at m = 1024, 2,000 sets of 3,000 elements:
-// 11.0 -> 1.7 ms (ProbMinHash2), 13.2 -> 8.4 ms (ProbMinHash4) against 4.
+// per SIMD), ProbMinHash4 5 (its per-step constants and the binary-weight
+// branch leave room for no more at 3 waves per SIMD).  Measured at m = 1024,
+// 2,000 sets of 3,000 elements: 11.0 -> 1.7 ms (ProbMinHash2), 13.2 -> 8.4 ms
+// (ProbMinHash4, 6 steps) against 4.
 template <int V>
-constexpr uint32_t kFyLaneSteps = V == 4 ? 6 : 16;
+constexpr uint32_t kFyLaneSteps = V == 4 ? 5 : 16;
 constexpr uint32_t kEpt = 2;                     // elements per thread per batch
 
 // Optional event counters (statistics build only, -DPMH_STATS): accumulated in
@@ -353,6 +354,9 @@ struct Round {
   const LogCell* lt;  // logarithm table (LDS copy)
 };
 
+// Weight of element p; binary sets (no weight array) have every weight 1.
+__device__ __forceinline__ double elem_w(const Round& R, uint32_t p) { return R.w ? R.w[p] : 1.0; }
+
 __device__ __forceinline__ uint64_t shared_kmax(Shared& sm) {
   return __hip_atomic_load(&sm.kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -460,7 +464,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         return step;
       }
       const uint64_t w0 = mix64(pb);
-      const double x = lb + winv * trunc_exp(w0, pb, lam, c1, c2, c3, t.expm1c);
+      const double x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, lam, c1, c2, c3, t.expm1c);
       const uint64_t key = make_key(x, p);
       PMH_STAT(sm, kStLanePts, 1);
       if (x >= R.Tprev && key < kmax) {
@@ -490,10 +494,12 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         if (!(x < R.T)) return (int)step + 1;
         if (make_key(x, p) >= kmax) return (int)step + 1;
       } else {
-        const double lb = winv * t.gam[i - 1];
+        const double lb = A.binary ? (double)(i - 1) : winv * t.gam[i - 1];
         if (!(lb < R.T)) return (int)step;
         if (make_key(lb, p) >= kmax) return (int)step;
-        if (i < m)
+        if (A.binary)
+          x = lb + u32v(w0);
+        else if (i < m)
           x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
         else
           x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
@@ -563,17 +569,19 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
         key = make_key(x, p);
       }
     } else {
       stop = !valid;
       if (valid) {
-        const double lb = winv * t.gam[i - 1];
+        const double lb = A.binary ? (double)(i - 1) : winv * t.gam[i - 1];
         stop = !(lb < R.T) || make_key(lb, p) >= kmax;
       }
       if (!stop) {
-        if (i < m)
+        if (A.binary)
+          x = (double)(i - 1) + u32v(w0);
+        else if (i < m)
           x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
         else
           x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
@@ -673,7 +681,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
         p = ce.p;
         i0 = ce.i;
         tacc = ce.tacc;
-        winv = 1.0 / R.w[p];
+        winv = 1.0 / elem_w(R, p);
         K = mix64(R.ids[p] ^ R.K0);
         pb = pbase(K, i0) + (uint64_t)j * kPointStep;
         have = true;
@@ -697,7 +705,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
         key = make_key(x, p);
       }
     }
@@ -741,7 +749,7 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
     e = (uint32_t)__shfl((int)e, 0);
     if (e >= qtail) break;
     const ChainEntry ce = q[e];
-    chain_elem<V>(A, R, ce, 1.0 / R.w[ce.p], mix64(R.ids[ce.p] ^ R.K0), keys, g, sm);
+    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), mix64(R.ids[ce.p] ^ R.K0), keys, g, sm);
   }
   PMH_TOC(sm, kStCycChain, t_chain);
   PMH_TIC(t_mini);
@@ -767,7 +775,7 @@ __device__ __forceinline__ Round set_round(const HashArgs& A, uint64_t set, uint
   const uint64_t n64 = b - a;
   Round R;
   R.ids = A.ids + a;
-  R.w = A.w + a;
+  R.w = A.w ? A.w + a : nullptr;
   R.n = (uint32_t)(n64 > kMaxSet ? 0 : n64);
   R.m = A.m;
   R.imax = A.imax;
@@ -791,7 +799,7 @@ __device__ double block_weight_sum(const HashArgs& A, const Round& R, uint32_t p
   double ws = 0.0;
   bool bad = false;
   for (uint32_t p = p0 + tid; p < p1; p += NW * 64) {
-    const double w = R.w[p];
+    const double w = elem_w(R, p);
     if (weight_ok(w)) ws += w;
     else if (w != 0.0) bad = true;
   }
@@ -831,7 +839,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
 #pragma unroll
   for (uint32_t k = 0; k < kEpt; ++k) {
     const uint32_t p = p0 + k * BS + tid;
-    wn[k] = kPrefetch && p < p1 ? R.w[p] : 0.0;
+    wn[k] = kPrefetch && p < p1 ? elem_w(R, p) : 0.0;
     idn[k] = kPrefetch && p < p1 ? R.ids[p] : 0;
   }
   for (uint32_t base = p0, nb = 0; base < p1; base += batch, ++nb) {
@@ -844,12 +852,12 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
         idc[k] = idn[k];
         const uint32_t p = base + batch + k * BS + tid;
         if (p < p1) {
-          wn[k] = R.w[p];
+          wn[k] = elem_w(R, p);
           idn[k] = R.ids[p];
         }
       } else {
         const uint32_t p = base + k * BS + tid;
-        wc[k] = p < p1 ? R.w[p] : 0.0;
+        wc[k] = p < p1 ? elem_w(R, p) : 0.0;
         idc[k] = 0;
       }
     }

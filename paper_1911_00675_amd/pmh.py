@@ -33,6 +33,7 @@ SIGNATURES = {
     "pmh_status_str": (ctypes.c_char_p, [_i32]),
     "pmh_hash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_pminhash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
+    "pmh_hash_sets_binary": (_i32, [_vp] * 3 + [_u64] + [_vp] * 5),
     "pmh_bbit_pack": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp]),
     "pmh_bbit_allpairs": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp]),
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
@@ -170,12 +171,23 @@ class Context:
         """Signatures of a CSR batch of device tensors (ids int64/uint64,
         weights float64, offsets int64/uint64 with num_sets+1 entries).
         mode: "batched", "plain", "graph" (ProbMinHash of the context's
-        variant) or "pminhash" (P-MinHash with the context's seed and m)."""
+        variant), "pminhash" (P-MinHash with the context's seed and m) or
+        "binary" (the unit-weight specialisation of the context's variant;
+        weights must be None)."""
         torch = _torch()
         num_sets = int(offsets.numel()) - 1
         if out is None:
             out = self.alloc_outputs(num_sets, outputs)
         i64 = (torch.int64, torch.uint64)
+        if mode == "binary":
+            if weights is not None:
+                raise ValueError("binary mode takes no weights")
+            rc = lib().pmh_hash_sets_binary(
+                self._c, _dptr(ids, i64, "ids"), _dptr(offsets, i64, "offsets"), num_sets,
+                _dptr(out.idx, (torch.int32,), "idx"), _dptr(out.val, (torch.float64,), "val"),
+                _dptr(out.id, i64, "id"), _dptr(out.keys, i64, "keys"), _stream_ptr(stream))
+            _check(rc, "pmh_hash_sets_binary")
+            return out
         fn = {"batched": lib().pmh_hash_sets, "plain": lib().pmh_hash_sets_plain,
               "graph": lib().pmh_hash_sets_graph, "pminhash": lib().pmh_pminhash_sets}[mode]
         rc = fn(self._c, _dptr(ids, i64, "ids"), _dptr(weights, (torch.float64,), "weights"),
