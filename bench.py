@@ -96,6 +96,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-break-even", action="store_true")
     ap.add_argument("--no-allpairs", action="store_true")
+    ap.add_argument("--no-binary", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--cpu-sets", type=int, default=3000)
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
@@ -116,6 +117,7 @@ def main():
         sys.exit(2)
     if args.profile:
         args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = args.no_allpairs = True
+        args.no_binary = True
     import torch
     from paper_1911_00675_amd import pmh, workloads as W
 
@@ -316,6 +318,33 @@ def main():
         del aid, afp
         log(f"allpairs: {allpairs}")
 
+    # ------------------------------------------- binary-weight specialisations
+    # Sec. 2.9: the same mixed batch without weights (every weight 1), each
+    # variant's persistent kernel timed weighted (unit weights) and binary.
+    binary = None
+    if not args.no_binary:
+        ones = torch.ones_like(w)
+        binary = {}
+        for v in (1, 2, 3, 4):
+            bc = ctxs[v] if v in ctxs else pmh.Context(SEED, M, v)
+            bo = outs[v] if v in outs else bc.alloc_outputs(S, ("idx", "val", "id"))
+            res = {}
+            for name, wts, mode in (("weighted_ms", ones, "batched"), ("binary_ms", None, "binary")):
+                bc.hash_sets(ids, wts, off, out=bo, mode=mode)
+                bc.timing_begin(3)
+                for _ in range(3):
+                    bc.hash_sets(ids, wts, off, out=bo, mode=mode)
+                res[name] = float(np.mean(bc.timing_read(3)))
+                if bc.status() != pmh.PMH_OK:
+                    raise RuntimeError(f"binary leg PMH{v} {mode}: status {bc.status()}")
+            res["binary_elements_per_s"] = N / (res["binary_ms"] * 1e-3)
+            res["weighted_over_binary"] = res["weighted_ms"] / res["binary_ms"]
+            binary[f"pmh{v}"] = res
+            if v not in ctxs:
+                bc.close()
+        del ones
+        log(f"binary: {binary}")
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -353,6 +382,7 @@ def main():
         "latency": latency,
         "break_even": break_even,
         "allpairs": allpairs,
+        "binary": binary,
     }
     print(json.dumps(out))
 
