@@ -150,11 +150,33 @@ int pmh_hash_sets_binary(pmh_ctx* ctx, const uint64_t* ids, const uint64_t* offs
                          uint32_t* out_idx, double* out_val, uint64_t* out_id, uint64_t* out_keys,
                          void* stream);
 
+/* Incremental signatures: adds a batch of new elements to num_sets sets
+ * whose signatures are kept across calls.  The signature is a componentwise
+ * minimum over the points of every element (eq. (1) and the structure of
+ * Sec. 2), so a set's elements can arrive in several calls: the result after
+ * any number of calls is, bit for bit, the pmh_hash_sets signature of the
+ * concatenation of all the batches in call order (element positions count
+ * from the set's first element ever).  keys [device, in/out]: num_sets x m
+ * keys, all-ones (empty) for a new set; counts [device, in/out]: elements
+ * each set has absorbed (0 for a new set), advanced by the batch's size.
+ * weights [device] or NULL for the binary specialisations (as
+ * pmh_hash_sets_binary).  out_idx, out_val [device] or NULL: position and
+ * value of the updated signature; out_id [device, in/out] or NULL: the ids
+ * from the previous call on the same rows (components that keep their
+ * element keep their id), so pass it on every call of a set or never.  Sets
+ * are not split across workgroups.  A set whose total would exceed 2^20
+ * elements (the position field) is left unchanged and reported as
+ * PMH_ERR_SET_TOO_LARGE by pmh_get_status.  Timed by pmh_timing_begin. */
+int pmh_update_sets(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                    uint64_t num_sets, uint32_t* counts, uint64_t* keys, uint32_t* out_idx, double* out_val,
+                    uint64_t* out_id, void* stream);
+
 /* Kernel timing for benchmarks.  After pmh_timing_begin(ctx, n) the next n
- * pmh_hash_sets (pmh_hash_sets_binary, pmh_pminhash_sets) calls record a HIP
- * event pair right around their persistent hash kernel, on the call's stream (the ordering and split-set kernels stay
- * outside).  pmh_timing_read waits for the n pairs and writes their durations
- * in milliseconds to [host] ms[0..n); PMH_ERR_NOT_READY if fewer than n calls
+ * pmh_hash_sets (pmh_hash_sets_binary, pmh_update_sets, pmh_pminhash_sets)
+ * calls record a HIP event pair right around their persistent hash kernel, on
+ * the call's stream (the ordering and split-set kernels stay outside).
+ * pmh_timing_read waits for the n pairs and writes their durations in
+ * milliseconds to [host] ms[0..n); PMH_ERR_NOT_READY if fewer than n calls
  * were recorded.  The events are owned by the context. */
 int pmh_timing_begin(pmh_ctx* ctx, int n);
 int pmh_timing_read(pmh_ctx* ctx, float* ms, int n);

@@ -73,6 +73,7 @@ struct HashArgs {
   int max_rounds, lane_budget, kmax_refresh;
   uint32_t qcap;             // chain queue entries in LDS (>= one batch)
   uint32_t binary;           // binary weights: no weight array, every weight 1 (Sec. 2.9 values for PMH3/4)
+  uint32_t* counts;          // update mode: elements each set has absorbed (in/out); null otherwise
   uint32_t* status;          // device status word
   const uint32_t* order;     // work list (set indices), heavy first
   uint32_t* counter;         // work counters (zeroed by the order kernel)

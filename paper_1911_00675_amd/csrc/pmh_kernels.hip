@@ -931,7 +931,14 @@ __device__ void set_rounds(const HashArgs& A, Round& R, double T, double Tprev, 
   }
 }
 
-// keys (LDS) -> (position, value, id) of the set's signature.
+// An update call's previous key as it seeds the LDS minima: position bits
+// cleared, so that on equal truncated values it stays ahead of every new
+// element (all of which come later in the set's element sequence).
+__device__ __forceinline__ uint64_t seed_key(uint64_t old) { return old == kEmptyKey ? old : old & ~kPosMask; }
+
+// keys (LDS) -> (position, value, id) of the set's signature.  Update mode
+// (A.counts): a component whose LDS key still equals its seed keeps the
+// previous key and id; one a new element won takes position base + p.
 template <int NW>
 __device__ void epilogue(const HashArgs& A, const Round& R, uint64_t set, const uint64_t* keys, Shared& sm) {
   constexpr int BS = NW * 64;
@@ -939,16 +946,28 @@ __device__ void epilogue(const HashArgs& A, const Round& R, uint64_t set, const 
   const uint32_t m = R.m;
   __syncthreads();
   const uint64_t o = set * (uint64_t)m;
+  const uint32_t base = A.counts ? A.counts[set] : 0u;  // re-read: not kept live through the rounds
   for (uint32_t k = tid; k < m; k += BS) {
-    const uint64_t key = keys[k];
+    uint64_t key = keys[k];
+    bool fresh = true;
+    if (A.counts) {
+      const uint64_t old = A.out_keys[o + k];
+      if (key == seed_key(old)) {
+        key = old;
+        fresh = false;
+      } else {
+        key = (key & ~kPosMask) | (uint64_t)(base + (uint32_t)(key & kPosMask));
+      }
+    }
     if (A.out_keys) A.out_keys[o + k] = key;
     const bool empty = key == kEmptyKey;
     const uint32_t pos = (uint32_t)(key & kPosMask);
     if (A.out_idx) A.out_idx[o + k] = empty ? 0xFFFFFFFFu : pos;
     if (A.out_val) A.out_val[o + k] = empty ? __longlong_as_double(0x7FF0000000000000ll)
                                             : __longlong_as_double((long long)(key & ~kPosMask));
-    if (A.out_id) A.out_id[o + k] = empty ? 0ull : R.ids[pos];
+    if (A.out_id && fresh) A.out_id[o + k] = empty ? 0ull : R.ids[pos - base];
   }
+  if (A.counts && tid == 0) A.counts[set] = base + R.n;
   __syncthreads();
 #ifdef PMH_STATS
   if (tid < kStCount && A.points) atomicAdd((unsigned long long*)&A.points[tid], (unsigned long long)sm.st[tid]);
@@ -960,9 +979,25 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
                             uint16_t* fy, const LogCell* lt, Shared& sm) {
   Round R = set_round<NW>(A, set, qcap, lt, sm);
   PMH_TIC(t_set);
-  for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = kEmptyKey;
+  uint64_t kmax0 = kEmptyKey;
+  if (A.counts) {
+    // Update: the new elements extend the set's element sequence after the
+    // elements it has absorbed; the previous keys seed the minima and the
+    // stop limit.  A sequence beyond the position field takes no element:
+    // the epilogue writes the set back as it was.
+    const uint64_t n64 = A.off[set + 1] - A.off[set];
+    if ((uint64_t)A.counts[set] + n64 > kMaxSet) {
+      if (threadIdx.x == 0) atomicOr(A.status, kStatusSetTooLarge);
+      R.n = 0;
+    }
+    const uint64_t o = set * (uint64_t)R.m;
+    for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = seed_key(A.out_keys[o + k]);
+    kmax0 = block_max_keys<NW>(keys, R.m, sm);
+  } else {
+    for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = kEmptyKey;
+  }
   const double W = block_weight_sum<NW>(A, R, 0, R.n, sm);
-  if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kEmptyKey, keys, q, fy, sm);
+  if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kmax0, keys, q, fy, sm);
   PMH_TOC(sm, kStCycSet, t_set);
   epilogue<NW>(A, R, set, keys, sm);
 }

@@ -367,6 +367,28 @@ int pmh_hash_sets_binary(pmh_ctx* c, const uint64_t* ids, const uint64_t* off, u
   return enqueue_batched(c, a, &c->work, (hipStream_t)stream, 0, 0, ev0, ev1);
 }
 
+int pmh_update_sets(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
+                    uint32_t* counts, uint64_t* keys, uint32_t* idx, double* val, uint64_t* id, void* stream) {
+  if (!c) return PMH_ERR_ARG;
+  if (num_sets == 0) return PMH_OK;
+  if (!off || !ids || !counts || !keys || num_sets >= 0xFFFFFFFFull) return PMH_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  int rc = ensure_work(c, &c->work, num_sets);
+  if (rc) return rc;
+  HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
+  a.binary = w ? 0u : 1u;
+  a.counts = counts;
+  a.split_log2 = 0;  // every set in one workgroup: its previous keys seed the minima in LDS
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->tnext < c->tcount) {
+    ev0 = c->tev[2 * c->tnext];
+    ev1 = c->tev[2 * c->tnext + 1];
+    c->tnext++;
+  }
+  return enqueue_batched(c, a, &c->work, (hipStream_t)stream, 0, 0, ev0, ev1);
+}
+
 int pmh_timing_begin(pmh_ctx* c, int n) {
   if (!c || n < 0 || n > 1 << 16) return PMH_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->mu);

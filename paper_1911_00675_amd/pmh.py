@@ -34,6 +34,7 @@ SIGNATURES = {
     "pmh_hash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_pminhash_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_binary": (_i32, [_vp] * 3 + [_u64] + [_vp] * 5),
+    "pmh_update_sets": (_i32, [_vp] * 4 + [_u64] + [_vp] * 6),
     "pmh_bbit_pack": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp]),
     "pmh_bbit_allpairs": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp]),
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
@@ -136,6 +137,14 @@ class Signatures:
     keys: object = None  # int64 [S, m], bit pattern of uint64
 
 
+@dataclass
+class SetState:
+    """Signatures kept across pmh_update_sets calls (device tensors)."""
+    keys: object          # int64 [S, m], all ones for a new set
+    counts: object        # int32 [S], elements absorbed (bit pattern of uint32)
+    id: object = None     # int64 [S, m] or None: ids of the components' elements
+
+
 class Context:
     """A signature context for (seed, m, variant) on the current device."""
 
@@ -196,6 +205,33 @@ class Context:
                 _dptr(out.id, i64, "id"), _dptr(out.keys, i64, "keys"), _stream_ptr(stream))
         _check(rc, f"pmh_hash_sets ({mode})")
         return out
+
+    def new_state(self, num_sets: int, with_id: bool = True) -> SetState:
+        """Empty signatures for num_sets sets that grow by update_sets."""
+        torch = _torch()
+        shape = (num_sets, self.m)
+        return SetState(keys=torch.full(shape, -1, dtype=torch.int64, device="cuda"),
+                        counts=torch.zeros(num_sets, dtype=torch.int32, device="cuda"),
+                        id=torch.zeros(shape, dtype=torch.int64, device="cuda") if with_id else None)
+
+    def update_sets(self, ids, weights, offsets, state: SetState, out: Signatures | None = None,
+                    stream=None) -> SetState:
+        """Add a CSR batch of new elements (weights None: binary weights) to the
+        sets of state, in place; out may receive positions and values."""
+        torch = _torch()
+        num_sets = int(offsets.numel()) - 1
+        if state.keys.shape != (num_sets, self.m) or state.counts.numel() != num_sets:
+            raise ValueError("state does not match the batch's sets or the context's m")
+        i64 = (torch.int64, torch.uint64)
+        rc = lib().pmh_update_sets(
+            self._c, _dptr(ids, i64, "ids"),
+            None if weights is None else _dptr(weights, (torch.float64,), "weights"),
+            _dptr(offsets, i64, "offsets"), num_sets, _dptr(state.counts, (torch.int32,), "counts"),
+            _dptr(state.keys, i64, "keys"), _dptr(out.idx if out else None, (torch.int32,), "idx"),
+            _dptr(out.val if out else None, (torch.float64,), "val"), _dptr(state.id, i64, "id"),
+            _stream_ptr(stream))
+        _check(rc, "pmh_update_sets")
+        return state
 
     def status(self, stream=None) -> int:
         """Synchronize and return (then clear) sticky kernel errors."""

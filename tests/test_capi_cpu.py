@@ -57,6 +57,7 @@ def test_argument_errors_without_device(lib):
     assert lib.pmh_hash_sets(None, None, None, None, 1, None, None, None, None, None) == 1
     assert lib.pmh_pminhash_sets(None, None, None, None, 1, None, None, None, None, None) == 1
     assert lib.pmh_hash_sets_binary(None, None, None, 1, None, None, None, None, None) == 1
+    assert lib.pmh_update_sets(None, None, None, None, 1, None, None, None, None, None, None) == 1
     assert lib.pmh_bbit_pack(None, 1, 8, 1, None, None) == 1
     assert lib.pmh_bbit_allpairs(None, 1, 8, 1, None, None) == 1
     assert lib.pmh_estimate(None, None, None, None, 4, None) == 1
