@@ -97,6 +97,7 @@ def parse():
     ap.add_argument("--no-break-even", action="store_true")
     ap.add_argument("--no-allpairs", action="store_true")
     ap.add_argument("--no-binary", action="store_true")
+    ap.add_argument("--no-update", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--cpu-sets", type=int, default=3000)
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
@@ -117,7 +118,7 @@ def main():
         sys.exit(2)
     if args.profile:
         args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = args.no_allpairs = True
-        args.no_binary = True
+        args.no_binary = args.no_update = True
     import torch
     from paper_1911_00675_amd import pmh, workloads as W
 
@@ -345,6 +346,48 @@ def main():
         del ones
         log(f"binary: {binary}")
 
+    # ------------------------------------------------ incremental signatures
+    # The mixed batch arriving in two calls (the first half of every set's
+    # elements, then the second): pmh_update_sets twice against one
+    # pmh_hash_sets call, persistent kernel time and whole calls.
+    update = None
+    if not args.no_update:
+        sizes_u = b.sizes().astype(np.int64)
+        local = np.arange(N, dtype=np.int64) - np.repeat(b.offsets[:-1].astype(np.int64), sizes_u)
+        first = local < np.repeat(sizes_u // 2, sizes_u)
+        halves = []
+        for sel, cnt in ((first, sizes_u // 2), (~first, sizes_u - sizes_u // 2)):
+            ho = np.concatenate([[0], np.cumsum(cnt)]).astype(np.uint64)
+            halves.append((pmh.to_device(b.ids[sel]), pmh.to_device(b.weights[sel]), pmh.to_device(ho)))
+        update = {"calls": 2, "split": "first half of every set, then the second"}
+        for v in VARIANTS:
+            st = ctxs[v].new_state(S, with_id=True)
+            ctxs[v].update_sets(*halves[0], st)
+            ctxs[v].update_sets(*halves[1], st)  # warm-up pair
+            torch.cuda.synchronize()
+            reps = 3
+            ctxs[v].timing_begin(2 * reps)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                st.keys.fill_(-1)
+                st.counts.zero_()
+                ctxs[v].update_sets(*halves[0], st)
+                ctxs[v].update_sets(*halves[1], st)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            kern = ctxs[v].timing_read(2 * reps).reshape(reps, 2)
+            if ctxs[v].status() != pmh.PMH_OK:
+                raise RuntimeError(f"update leg PMH{v}: status {ctxs[v].status()}")
+            update[f"pmh{v}"] = {"kernel_ms_per_call": [float(kern[:, 0].mean()), float(kern[:, 1].mean())],
+                                 "kernel_ms_total": float(kern.sum(axis=1).mean()),
+                                 "one_call_kernel_ms": launch_ms[v],
+                                 "wall_ms_two_calls": e0.elapsed_time(e1) / reps,
+                                 "elements_per_s": N / (float(kern.sum(axis=1).mean()) * 1e-3)}
+            del st
+        del halves
+        log(f"update: {update}")
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -383,6 +426,7 @@ def main():
         "break_even": break_even,
         "allpairs": allpairs,
         "binary": binary,
+        "update": update,
     }
     print(json.dumps(out))
 

@@ -186,7 +186,7 @@ def sign(variant: int, seed: int, m: int, ids, weights, mode: int = MODE_SEQUENT
     w = np.ascontiguousarray(weights, dtype=np.float64)
     assert ids.shape == w.shape
     keys = np.zeros(m, dtype=np.uint64)
-    stats = np.zeros(2, dtype=np.uint64)
+    stats = np.zeros(3, dtype=np.uint64)  # points, labels, interleaved buffer size after pass 1
     rc = lib().or_sign(mode, variant, seed & EMPTY, m, _ptr(ids), _ptr(w), ids.size, _ptr(keys),
                        _ptr(stats))
     if rc:

@@ -424,6 +424,7 @@ static inline void o_tree_update(uint64_t *q, uint32_t m, uint32_t k1, uint64_t 
 typedef struct {
     uint64_t points; /* points generated */
     uint64_t labels; /* labels drawn */
+    uint64_t buffer; /* interleaved: elements in the buffer after the first pass (its maximum) */
 } o_stats;
 
 static inline uint64_t o_elem_key(uint64_t seedhash, uint64_t id) { return o_mix64(id ^ seedhash); }
@@ -565,6 +566,7 @@ static int o_sign_interleaved(const o_params *P, uint64_t seedhash, const uint64
             buf[s++] = (o_live){p, winv, K, 1, 0, h};
         }
     }
+    st->buffer = s; /* the buffer only shrinks from here (Sec. 2.7 space analysis) */
     while (s > 0) {
         uint32_t t = 0;
         for (uint32_t j = 0; j < s; ++j) {
@@ -714,7 +716,8 @@ int or_stream(int variant, uint32_t m, uint64_t K, double winv, uint64_t count, 
 }
 
 /* mode 0: sequential (Sec. 2.3-2.6), 1: interleaved (Sec. 2.7, PMH1/PMH3
- * only), 2: brute force.  keys[m] out; stats[2] = {points, labels}. */
+ * only), 2: brute force.  keys[m] out; stats[3] = {points, labels, buffer
+ * size after the first pass (interleaved mode, else 0)}. */
 int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
             uint64_t n, uint64_t *keys, uint64_t *stats) {
     if ((!ids || !w) && n) return O_ERR_ARG;
@@ -726,7 +729,7 @@ int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *id
     if (rc) return rc;
     if (mode == 1 && P.variant != 1 && P.variant != 3) { o_params_free(&P); return O_ERR_ARG; }
     uint64_t sh = o_mix64(seed);
-    o_stats st = {0, 0};
+    o_stats st = {0, 0, 0};
     if (mode == 2) {
         rc = o_sign_brute(&P, sh, ids, w, (uint32_t)n, keys, &st);
     } else {
@@ -740,7 +743,7 @@ int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *id
         free(q);
         o_perm_free(&F);
     }
-    if (stats) { stats[0] = st.points; stats[1] = st.labels; }
+    if (stats) { stats[0] = st.points; stats[1] = st.labels; stats[2] = st.buffer; }
     o_params_free(&P);
     return rc;
 }
@@ -860,7 +863,7 @@ static void *o_batch_worker(void *arg) {
     uint64_t *q = malloc(sizeof(uint64_t) * 2 * m);
     o_perm F;
     int rc = o_perm_init(&F, m);
-    o_stats st = {0, 0};
+    o_stats st = {0, 0, 0};
     if (q && !rc) {
         for (;;) {
             uint64_t s = __atomic_fetch_add(&B->next, 1, __ATOMIC_RELAXED);
