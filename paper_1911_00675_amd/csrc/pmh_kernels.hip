@@ -39,13 +39,23 @@ namespace {
 constexpr double kLn2Hi = 0x1.62e42fefa0000p-1;  // ln 2 rounded to 36 bits
 constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
 // Lane-mode Fisher-Yates steps kept in registers: ProbMinHash2 16 (3 waves
-// per SIMD), ProbMinHash4 5 (its per-step constants and the binary-weight
-// branch leave room for no more at 3 waves per SIMD).  Measured at m = 1024,
-// 2,000 sets of 3,000 elements: 11.0 -> 1.7 ms (ProbMinHash2), 13.2 -> 8.4 ms
-// (ProbMinHash4, 6 steps) against 4.
+// per SIMD), ProbMinHash4 4 (its per-step constants, the binary-weight branch
+// and the chain-mode tables leave room for no more at 3 waves per SIMD).
+// Measured at m = 1024, 2,000 sets of 3,000 elements with the earlier
+// readlane search in chain mode: 11.0 -> 1.7 ms (ProbMinHash2, 16 steps
+// against 4), 13.2 -> 8.4 ms (ProbMinHash4, 6 against 4).
 template <int V>
-constexpr uint32_t kFyLaneSteps = V == 4 ? 5 : 16;
+constexpr uint32_t kFyLaneSteps = V == 4 ? 4 : 16;
 constexpr uint32_t kEpt = 2;                     // elements per thread per batch
+// Per-wave tables that resolve the dependencies of a chain-mode tile of 64
+// Fisher-Yates steps (ProbMinHash2/4): win[r] = 1 + the latest step of the
+// tile that drew slot P0 + r of its position window, bkt[h] = the steps whose
+// slot hashes to h.  All zero between tiles.
+constexpr int kFyBuckets = 128;
+struct FyScratch {
+  uint64_t bkt[kFyBuckets];
+  uint32_t win[64];
+};
 
 // Optional event counters (statistics build only, -DPMH_STATS): accumulated in
 // LDS per workgroup and added to HashArgs::points[0..15] when a set ends.
@@ -528,7 +538,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
 // until a point reaches R.T or the stop limit.
 template <int V>
 __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, double winv, uint64_t K,
-                           uint64_t* keys, uint16_t* g, Shared& sm) {
+                           uint64_t* keys, uint16_t* g, FyScratch* fs, Shared& sm) {
   const Tables& t = A.t;
   const int lane = threadIdx.x & 63;
   const uint32_t m = R.m;
@@ -601,27 +611,61 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       if (apply) label = lemire(w0, pb, m);
     } else {
       // 64 Fisher-Yates steps at once.  Step L (point i0+L) consumes position
-      // P = i-1 and draws slot j >= P; its label is g[j] and it writes the old
-      // g[P] into slot j.  Dependencies inside the tile are resolved by finding,
-      // for each step, the latest earlier step that wrote its slot or position.
+      // P = i-1 and draws slot j >= P; its label is g[j] as the latest earlier
+      // step drawing slot j left it (else the tile's initial g[j]), and it
+      // writes into slot j the value g[P] held before it: the value the latest
+      // earlier step drawing slot P wrote (else the initial g[P]).  No later
+      // step draws slot P (its slots lie at or above its own position > P),
+      // and a step drawing its own position (j = P) changes nothing later
+      // steps see, so only j > P enters the window table.  The tables find
+      // those latest steps; chains of steps writing each other's positions
+      // are resolved by pointer jumping.
       const int P = (int)i - 1;
       const int j = active ? P + (int)lemire(w0, pb, m - i + 1) : -1;
-      int lastJ = -1, lastP = -1;
-      bool later = false;
-      for (int s = 0; s < 64; ++s) {
-        const int js = __builtin_amdgcn_readlane(j, s);
-        if (s < lane) {
-          if (js == j) lastJ = s;
-          if (js == P) lastP = s;
-        } else if (s > lane && js == j) {
-          later = true;
+      const int r = j - ((int)i0 - 1);  // window index of slot j (>= lane)
+      const int h = j & (kFyBuckets - 1);
+      const bool inwin = active && j != P && r < 64;
+      // the lane's bit and table address are rebuilt per tile: hoisted out of
+      // the loop they stay live through the point generation (+8 VGPRs)
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      const uint64_t bit = 1ull << ln;
+      if (inwin)
+        __hip_atomic_fetch_max(&fs->win[r], (uint32_t)ln + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (active) __hip_atomic_fetch_or(&fs->bkt[h], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const int lastP = active ? (int)fs->win[ln] - 1 : -1;  // an earlier step (j > P above)
+      uint64_t mates = active ? fs->bkt[h] & ~bit : 0ull;
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (inwin) fs->win[r] = 0u;
+      if (active) fs->bkt[h] = 0ull;
+      // Among the bucket mates (highest lane first): a later step with the
+      // same slot (bit 8 of jl), and the latest earlier one (jl & 0xFF, 0xFF:
+      // none).
+      int jl = 0xFF;
+      while (__builtin_amdgcn_ballot_w64(mates != 0ull)) {
+        const int c = mates ? 63 - __builtin_clzll(mates) : lane;
+        const int jc = __shfl(j, c);
+        if (mates) {
+          mates &= ~(1ull << c);
+          if (jc == j) {
+            if (c > lane) {
+              jl |= 0x100;
+            } else {
+              jl = (jl & 0x100) | c;
+              mates = 0ull;
+            }
+          }
         }
       }
+      const int lastJ = (jl & 0xFF) == 0xFF ? -1 : (jl & 0xFF);
+      const bool later = (jl & 0x100) != 0;
       const int gj = active ? (int)g[j] : 0;
       const int gp = active ? (int)g[P] : 0;
       int v = gp, ptr = lastP;  // value step L writes = g[P] at step L
-#pragma unroll
-      for (int r = 0; r < 6; ++r) {
+      while (__builtin_amdgcn_ballot_w64(ptr >= 0)) {
         const int src = ptr >= 0 ? ptr : lane;
         const int vv = __shfl(v, src);
         const int pp = __shfl(ptr, src);
@@ -740,7 +784,10 @@ template <int V, int NW>
 __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, ChainEntry* q, uint16_t* fy,
                            Shared& sm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint16_t* g = (V == 2 || V == 4) ? fy + (size_t)wv * R.m : nullptr;
+  // fy: NW FyScratch tables, then NW Fisher-Yates arrays of m labels
+  FyScratch* fs = (V == 2 || V == 4) ? reinterpret_cast<FyScratch*>(fy) + wv : nullptr;
+  uint16_t* g = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(reinterpret_cast<FyScratch*>(fy) + NW) + (size_t)wv * R.m
+                                   : nullptr;
   const uint32_t qtail = sm.qtail;
   PMH_TIC(t_chain);
   for (;;) {  // long streams first
@@ -749,7 +796,7 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
     e = (uint32_t)__shfl((int)e, 0);
     if (e >= qtail) break;
     const ChainEntry ce = q[e];
-    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), mix64(R.ids[ce.p] ^ R.K0), keys, g, sm);
+    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), mix64(R.ids[ce.p] ^ R.K0), keys, g, fs, sm);
   }
   PMH_TOC(sm, kStCycChain, t_chain);
   PMH_TIC(t_mini);
@@ -1072,6 +1119,10 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
                           : nullptr;
   const LogCell* src = reinterpret_cast<const LogCell*>(A.t.ltab);
   for (uint32_t k = threadIdx.x; k < kLogCells; k += NW * 64) lt[k] = src[k];
+  if constexpr (V == 2 || V == 4) {
+    uint64_t* z = reinterpret_cast<uint64_t*>(fy);
+    for (uint32_t k = threadIdx.x; k < NW * sizeof(FyScratch) / 8; k += NW * 64) z[k] = 0ull;
+  }
   __syncthreads();
 }
 
@@ -1642,7 +1693,7 @@ uint32_t batch_size(int waves) { return kEpt * (uint32_t)waves * 64; }
 
 size_t lds_bytes_q(int variant, uint32_t m, int waves, uint32_t qcap) {
   size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry);
-  if (variant == 2 || variant == 4) b += (size_t)waves * m * 2;
+  if (variant == 2 || variant == 4) b += (size_t)waves * (sizeof(FyScratch) + (size_t)m * 2);
   return b;
 }
 
