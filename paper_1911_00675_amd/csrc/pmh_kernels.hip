@@ -552,7 +552,18 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
   if constexpr (V == 2 || V == 4) {
     i0 = 1;
     tacc = 0;
-    for (uint32_t k = lane; k < m; k += 64) g[k] = (uint16_t)k;
+    {
+      // 8 labels per 16-byte store where 8 | m (the array is then 16-byte aligned)
+      const uint32_t n8 = (m & 7u) == 0 ? m >> 3 : 0u;
+      uint4* g8 = reinterpret_cast<uint4*>(g);
+      for (uint32_t c = lane; c < n8; c += 64) {
+        uint32_t a = c << 3;
+        asm volatile("" : "+v"(a));
+        a |= (a + 1u) << 16;
+        g8[c] = make_uint4(a, a + 0x00020002u, a + 0x00040004u, a + 0x00060006u);
+      }
+      for (uint32_t k = (n8 << 3) + lane; k < m; k += 64) g[k] = (uint16_t)k;
+    }
     __builtin_amdgcn_wave_barrier();
   }
   uint64_t pb = pbase(K, i0) + (uint64_t)lane * kPointStep;
