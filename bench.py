@@ -98,6 +98,7 @@ def parse():
     ap.add_argument("--no-allpairs", action="store_true")
     ap.add_argument("--no-binary", action="store_true")
     ap.add_argument("--no-update", action="store_true")
+    ap.add_argument("--no-skewed", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=6000)
     ap.add_argument("--cpu-sets", type=int, default=3000)
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
@@ -118,7 +119,7 @@ def main():
         sys.exit(2)
     if args.profile:
         args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = args.no_allpairs = True
-        args.no_binary = args.no_update = True
+        args.no_binary = args.no_update = args.no_skewed = True
     import torch
     from paper_1911_00675_amd import pmh, workloads as W
 
@@ -388,6 +389,32 @@ def main():
         del halves
         log(f"update: {update}")
 
+    # ------------------------------------------------------- skewed batch
+    # 10,000 sets, 90% of 10-100 elements and 10% of 10^5-10^6 (split across
+    # workgroups), uniform(0,1] weights, m = 4096, all four variants: the
+    # persistent kernel timed with HIP events, two calls each after a warm-up.
+    skewed = None
+    if not args.no_skewed:
+        sb = W.skewed()
+        sids, sw, soff = pmh.to_device(sb.ids), pmh.to_device(sb.weights), pmh.to_device(sb.offsets)
+        skewed = {"num_sets": sb.num_sets, "num_elements": sb.num_elements, "m": 4096}
+        for v in (1, 2, 3, 4):
+            sc = pmh.Context(SEED, 4096, v)
+            so = sc.alloc_outputs(sb.num_sets, ("idx", "val"))
+            sc.hash_sets(sids, sw, soff, out=so)
+            sc.timing_begin(2)
+            for _ in range(2):
+                sc.hash_sets(sids, sw, soff, out=so)
+            kms = float(np.mean(sc.timing_read(2)))
+            if sc.status() != pmh.PMH_OK:
+                raise RuntimeError(f"skewed leg PMH{v}: status {sc.status()}")
+            skewed[f"pmh{v}"] = {"kernel_ms": kms, "elements_per_s": sb.num_elements / (kms * 1e-3),
+                                 "waves": sc.get_tuning().waves}
+            sc.close()
+            del so
+        del sids, sw, soff, sb
+        log(f"skewed: {skewed}")
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -427,6 +454,7 @@ def main():
         "allpairs": allpairs,
         "binary": binary,
         "update": update,
+        "skewed": skewed,
     }
     print(json.dumps(out))
 

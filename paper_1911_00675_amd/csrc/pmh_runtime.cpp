@@ -226,6 +226,11 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
     c->tune.grow = 1.35;
     c->tune.max_rounds = 8;
   }
+  // A workgroup holds m 8-byte keys in LDS: past m ~ 1,536 two-wave
+  // workgroups leave SIMDs with under 2 waves each, and four-wave ones keep
+  // 3 or more (skewed batch at m = 4096: ProbMinHash1 17.8 -> 9.7 ms,
+  // ProbMinHash3 16.3 -> 8.8 ms; at m = 1024 two waves stay ahead).
+  if (m > 1536) c->tune.waves = 4;
   c->device = dev;
   c->lds_limit = lim;
   hipDeviceProp_t prop;
