@@ -229,7 +229,8 @@ def test_schedule_invariance(pmh, variant):
                dict(chain_expect=1e9, mini_expect=1e9, lane_budget=1000000), dict(lane_budget=1),
                dict(mini_expect=0.0), dict(mini_expect=0.0, chain_expect=1e9), dict(waves=1), dict(waves=2),
                dict(lane_budget=1, waves=1),
-               dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0),
+               dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0), dict(waves=4),
+               dict(waves=4, chain_expect=0.0),
                dict(kmax_refresh=3, max_rounds=1),
                # many thin rounds (ProbMinHash3 resumes each element near the
                # previous threshold) in every mode
@@ -291,6 +292,31 @@ def test_split_sets(pmh, variant, m):
                     if "id" in got:
                         assert np.array_equal(got["id"][s].view(np.uint64), rid), (cfg, mode, outputs, s)
         ctx.set_tuning(**default)
+    ctx.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_large_m_four_waves(pmh, variant):
+    """m = 4096, where contexts default to 4 waves per workgroup: ragged sets
+    up to 40,000 elements (split ones included) in the batched and graph
+    forms, and the same keys with 1 and 2 waves."""
+    print(f"m=4096 PMH{variant}", flush=True)
+    m = 4096
+    rng = np.random.default_rng(70 + variant)
+    sizes = [0, 1, 3, 50, 700, 4096, 9000, 40000, 12, 2]
+    ids = rng.integers(0, 2**64 - 1, size=sum(sizes), dtype=np.uint64)
+    w = rng.uniform(size=sum(sizes)) + 1e-3
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    b = W.Batch(ids, w, off)
+    want = O.sign_batch(variant, SEED, m, ids, w, off, nthreads=8)
+    ctx = pmh.Context(SEED, m, variant)
+    assert ctx.get_tuning().waves == 4
+    for cfg in (dict(), dict(split_log2=12), dict(waves=2), dict(waves=1)):
+        ctx.set_tuning(**cfg)
+        for mode in ("batched", "graph"):
+            sig, st = _keys(ctx, b, mode)
+            assert st == pmh.PMH_OK
+            assert np.array_equal(_host(sig)[0], want), (cfg, mode)
     ctx.close()
 
 
