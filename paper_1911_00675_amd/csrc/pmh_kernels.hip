@@ -52,6 +52,12 @@ constexpr uint32_t kEpt = 2;                     // elements per thread per batc
 // tile that drew slot P0 + r of its position window, bkt[h] = the steps whose
 // slot hashes to h.  All zero between tiles.
 constexpr int kFyBuckets = 128;
+// Waves of a workgroup that run ProbMinHash2/4 chain elements, each with its
+// own label array u16[m] and tables; the others skip the chain pass.  At
+// m = 4096 four arrays took a four-wave workgroup to 81 KB of LDS (one per
+// CU); two leave room for two.
+constexpr int kFyWaves = 2;
+__host__ __device__ constexpr int fy_waves(int nw) { return nw < kFyWaves ? nw : kFyWaves; }
 struct FyScratch {
   uint64_t bkt[kFyBuckets];
   uint32_t win[64];
@@ -795,13 +801,15 @@ template <int V, int NW>
 __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, ChainEntry* q, uint16_t* fy,
                            Shared& sm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // fy: NW FyScratch tables, then NW Fisher-Yates arrays of m labels
+  // fy: fy_waves(NW) FyScratch tables, then as many label arrays of m
+  constexpr int NF = fy_waves(NW);
   FyScratch* fs = (V == 2 || V == 4) ? reinterpret_cast<FyScratch*>(fy) + wv : nullptr;
-  uint16_t* g = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(reinterpret_cast<FyScratch*>(fy) + NW) + (size_t)wv * R.m
+  uint16_t* g = (V == 2 || V == 4) ? reinterpret_cast<uint16_t*>(reinterpret_cast<FyScratch*>(fy) + NF) + (size_t)wv * R.m
                                    : nullptr;
   const uint32_t qtail = sm.qtail;
   PMH_TIC(t_chain);
-  for (;;) {  // long streams first
+  // waves without a label array take no chain element (wave-uniform)
+  for (; !((V == 2 || V == 4) && wv >= NF);) {  // long streams first
     uint32_t e = 0;
     if (lane == 0) e = atomicAdd(&sm.qhead, 1u);
     e = (uint32_t)__shfl((int)e, 0);
@@ -1132,7 +1140,7 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
   for (uint32_t k = threadIdx.x; k < kLogCells; k += NW * 64) lt[k] = src[k];
   if constexpr (V == 2 || V == 4) {
     uint64_t* z = reinterpret_cast<uint64_t*>(fy);
-    for (uint32_t k = threadIdx.x; k < NW * sizeof(FyScratch) / 8; k += NW * 64) z[k] = 0ull;
+    for (uint32_t k = threadIdx.x; k < fy_waves(NW) * sizeof(FyScratch) / 8; k += NW * 64) z[k] = 0ull;
   }
   __syncthreads();
 }
@@ -1704,7 +1712,7 @@ uint32_t batch_size(int waves) { return kEpt * (uint32_t)waves * 64; }
 
 size_t lds_bytes_q(int variant, uint32_t m, int waves, uint32_t qcap) {
   size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry);
-  if (variant == 2 || variant == 4) b += (size_t)waves * (sizeof(FyScratch) + (size_t)m * 2);
+  if (variant == 2 || variant == 4) b += (size_t)fy_waves(waves) * (sizeof(FyScratch) + (size_t)m * 2);
   return b;
 }
 
