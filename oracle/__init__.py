@@ -6,12 +6,13 @@ links or calls anything here, and nothing here calls the product library.
 
 Two layers:
 
-* ``liboracle.so`` (``pmh_oracle.c``): the sequential algorithms ProbMinHash1-4
-  (Sec. 2.3-2.6) with the stop-limit tree (Sec. 2.2) and the lazy
-  Fisher-Yates generator (Sec. 2.4), the interleaved ProbMinHash1a/3a
-  (Sec. 2.7), a brute-force signature (eq. (1) with the hash values of
-  eq. (9)), P-MinHash (Sec. 1.1, the paper's O(nm) baseline), the b-bit
-  reduction of Sec. 1.3 and the random-stream primitives.
+* ``liboracle.so`` (``pmh_oracle.c``): ProbMinHash1-4 (Sec. 2.3-2.6) as one
+  stream-consuming loop with the stop rule of Sec. 2 and the per-variant lower
+  bounds of Sec. 2.5/2.6, the lazily initialised random permutation of
+  Sec. 2.4, the interleaved ProbMinHash1a/3a (Sec. 2.7), a brute-force
+  signature (eq. (1) with the hash values of eq. (9)), P-MinHash (Sec. 1.1,
+  the paper's O(nm) baseline), the b-bit reduction of Sec. 1.3 and the
+  random-stream primitives, with the loop caps of Sec. 3 as parameters.
 * numpy functions below: the probability Jaccard similarity J_P written out
   from its definition (Sec. 1.1, "Incorporating Weights"), an O(N log N) form
   of it, the estimator of eq. (3), SuperMinHash's variance factor alpha(m, u)
@@ -65,11 +66,14 @@ def lib():
             "or_log_stream": (dbl, [dbl]), "or_log_table": (None, [vp]),
             "or_seedhash": (u64, [u64]), "or_mix64": (u64, [u64]),
             "or_word": (u64, [u64, u64, ctypes.c_uint]), "or_exp1_word": (dbl, [u64]),
-            "or_lemire": (u32, [u64, u64, u32]), "or_te": (dbl, [u64, u64, dbl, dbl, dbl, dbl]),
+            "or_lemire": (u32, [u64, u64, u32, ctypes.c_uint, u32]),
+            "or_te": (dbl, [u64, u64, dbl, dbl, dbl, ctypes.c_uint]),
             "or_key": (u64, [dbl, u32]), "or_imax": (u64, [u32]),
             "or_constants": (i32, [i32, u32, u32, vp]),
-            "or_stream": (i32, [i32, u32, u64, dbl, u64, vp, vp]),
+            "or_stream": (i32, [i32, u32, u64, dbl, u64, vp, vp, vp]),
             "or_sign": (i32, [i32, i32, u64, u32, vp, vp, u64, vp, vp]),
+            "or_sign_capped": (i32, [i32, i32, u64, u32, vp, vp, u64, vp, vp, vp]),
+            "or_sign_batch_capped": (i32, [i32, u64, u32, vp, vp, vp, u64, vp, i32, vp, vp]),
             "or_decode": (None, [vp, u64, vp, vp, vp, vp]),
             "or_sign_batch": (i32, [i32, u64, u32, vp, vp, vp, u64, vp, i32, vp]),
             "or_pminhash": (i32, [u64, u32, vp, vp, u64, vp]),
@@ -142,12 +146,15 @@ def exp1_of_word(w: int) -> float:
     return lib().or_exp1_word(w)
 
 
-def lemire(K: int, i: int, s: int) -> int:
-    return lib().or_lemire(K, i, s)
+def lemire(K: int, i: int, s: int, redraws: int = 8, floor: int = 0) -> int:
+    """Uniform label in [0, s) of point i (Lemire), at most `redraws` redraws;
+    floor > 0 also redraws every low product half below it (validation)."""
+    return lib().or_lemire(K, i, s, redraws, floor)
 
 
-def trunc_exp(K: int, i: int, lam: float, c1: float, c2: float, c3: float) -> float:
-    return lib().or_te(K, i, lam, c1, c2, c3)
+def trunc_exp(K: int, i: int, lam: float, a: float, c1: float, rounds: int = 32) -> float:
+    """Exp(lam; 0, 1) variate of point i (Sec. 2.8), a = e^lam - 1, c1 = a/lam."""
+    return lib().or_te(K, i, lam, a, c1, rounds)
 
 
 def key(x: float, p: int) -> int:
@@ -166,11 +173,33 @@ def constants(variant: int, m: int, i: int = 0) -> np.ndarray:
     return out
 
 
-def stream(variant: int, m: int, K: int, winv: float, count: int):
+class Caps:
+    """Loop caps of the streams (Sec. 3 advises bounding every loop): imax
+    points per ProbMinHash1/3 element (0: the default 6 m bitlen(m) + 64),
+    te_rounds proposals of the truncated-exponential sampler (1..32), redraws
+    of Lemire's method (0..8), and lemire_floor, a validation-only switch that
+    forces redraws of every draw whose low product half lies below it."""
+
+    def __init__(self, imax: int = 0, te_rounds: int = 32, redraws: int = 8, lemire_floor: int = 0):
+        self.imax, self.te_rounds, self.redraws, self.lemire_floor = imax, te_rounds, redraws, lemire_floor
+
+    def array(self):
+        return np.array([self.imax, self.te_rounds, self.redraws, self.lemire_floor], dtype=np.uint64)
+
+
+def _caps_ptr(caps):
+    if caps is None:
+        return None, None
+    a = caps.array()
+    return a, _ptr(a)
+
+
+def stream(variant: int, m: int, K: int, winv: float, count: int, caps: Caps | None = None):
     """Values and labels of points 1..count of one element's stream."""
     xs = np.zeros(count, dtype=np.float64)
     ls = np.zeros(count, dtype=np.uint32)
-    rc = lib().or_stream(variant, m, K, winv, count, _ptr(xs), _ptr(ls))
+    keep, cp = _caps_ptr(caps)
+    rc = lib().or_stream(variant, m, K, winv, count, _ptr(xs), _ptr(ls), cp)
     if rc:
         raise OracleError(rc)
     return xs, ls
@@ -180,22 +209,23 @@ def stream(variant: int, m: int, K: int, winv: float, count: int):
 # signatures
 
 def sign(variant: int, seed: int, m: int, ids, weights, mode: int = MODE_SEQUENTIAL,
-         return_stats: bool = False):
+         return_stats: bool = False, caps: Caps | None = None):
     """Keys (uint64[m]) of one weighted set."""
     ids = np.ascontiguousarray(ids, dtype=np.uint64)
     w = np.ascontiguousarray(weights, dtype=np.float64)
     assert ids.shape == w.shape
     keys = np.zeros(m, dtype=np.uint64)
     stats = np.zeros(3, dtype=np.uint64)  # points, labels, interleaved buffer size after pass 1
-    rc = lib().or_sign(mode, variant, seed & EMPTY, m, _ptr(ids), _ptr(w), ids.size, _ptr(keys),
-                       _ptr(stats))
+    keep, cp = _caps_ptr(caps)
+    rc = lib().or_sign_capped(mode, variant, seed & EMPTY, m, _ptr(ids), _ptr(w), ids.size, _ptr(keys),
+                              _ptr(stats), cp)
     if rc:
         raise OracleError(rc)
     return (keys, stats) if return_stats else keys
 
 
 def sign_batch(variant: int, seed: int, m: int, ids, weights, offsets, nthreads: int = 1,
-               return_stats: bool = False):
+               return_stats: bool = False, caps: Caps | None = None):
     """Keys (uint64[num_sets, m]) of a CSR batch, sequential algorithm per set."""
     ids = np.ascontiguousarray(ids, dtype=np.uint64)
     w = np.ascontiguousarray(weights, dtype=np.float64)
@@ -203,8 +233,9 @@ def sign_batch(variant: int, seed: int, m: int, ids, weights, offsets, nthreads:
     S = off.size - 1
     keys = np.zeros((S, m), dtype=np.uint64)
     stats = np.zeros(2, dtype=np.uint64)
-    rc = lib().or_sign_batch(variant, seed & EMPTY, m, _ptr(ids), _ptr(w), _ptr(off), S,
-                             _ptr(keys), int(nthreads), _ptr(stats))
+    keep, cp = _caps_ptr(caps)
+    rc = lib().or_sign_batch_capped(variant, seed & EMPTY, m, _ptr(ids), _ptr(w), _ptr(off), S,
+                                    _ptr(keys), int(nthreads), _ptr(stats), cp)
     if rc:
         raise OracleError(rc)
     return (keys, stats) if return_stats else keys

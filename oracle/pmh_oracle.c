@@ -17,26 +17,31 @@
  *     SplitMix64 word stream, an atanh-series logarithm and Lemire's bounded
  *     integers (the readings of Sec. 3's PRNG remarks listed in the design
  *     notes);
- *   * the truncated-exponential sampler of Sec. 2.8 (algorithm "Fast
- *     generation of random values from Exp(lambda;0,1)");
- *   * the sequential algorithms ProbMinHash1-4 (Sec. 2.3-2.6) with the
- *     binary-tree stop-limit maintenance of Sec. 2.2 and the lazy Fisher-Yates
- *     generator of Sec. 2.4, transcribed into a 64-bit (value, position) key
+ *   * the truncated exponential Exp(lambda; 0, 1) of Sec. 2.8, sampled by a
+ *     scheme derived here from its density (uniform part plus a rejection
+ *     step bounded by the tangent and the chord of expm1);
+ *   * ProbMinHash1-4 (Sec. 2.3-2.6): one loop consumes an element's stream
+ *     point by point and stops once a lower bound of its remaining points
+ *     reaches the stop limit max_k q_k (Sec. 2), the bounds being the points
+ *     themselves for the exponential-spacing streams and the interval starts
+ *     of Sec. 2.5/2.6; labels by Lemire's method or by the lazily initialised
+ *     permutation of Sec. 2.4; everything in a 64-bit (value, position) key
  *     space;
- *   * the interleaved variants ProbMinHash1a and ProbMinHash3a (Sec. 2.7);
+ *   * the interleaved variants ProbMinHash1a and ProbMinHash3a (Sec. 2.7): the
+ *     same step applied in passes over the live elements;
  *   * a brute-force reference that generates every point of every element's
  *     stream with no stop rule and takes the per-label minimum, i.e. the
- *     signature definition of eq. (1) with the hash values of eq. (9).
+ *     signature definition of eq. (1) with the hash values of eq. (9);
+ *   * the loop caps Sec. 3 recommends (stream length, sampler proposals,
+ *     Lemire redraws) as parameters, so that the capped paths can be forced.
  *
- * Pins (see tests/): sequential == brute force == interleaved on tiny inputs;
- * logarithm/expm1/log1p against the C library within a few ulp; Exp(1),
- * truncated-exponential, Lemire and Fisher-Yates distribution tests; the
- * collision law Pr(z_k(A) = z_k(B)) = J_P; the relative-MSE band of Sec. 3.1;
- * SuperMinHash's alpha(m,u) for ProbMinHash4 with equal weights (Sec. 2.9).
- * parity unpinned: the exact bit pattern of the word stream (SplitMix64 output
- * function applied to K + (c+1)*phi) has no published test vector available
- * offline; it is pinned only by its stated definition and by the statistical
- * tests above.
+ * Pins (see tests/): the word stream against the published SplitMix64 output
+ * sequence; sequential == brute force == interleaved on tiny inputs, also
+ * under forced caps; logarithm/expm1/log1p against the C library within a few
+ * ulp; Exp(1), truncated-exponential, Lemire and permutation distribution
+ * tests; the collision law Pr(z_k(A) = z_k(B)) = J_P; the relative-MSE band of
+ * Sec. 3.1; SuperMinHash's alpha(m,u) (exact closed forms) for ProbMinHash4
+ * with equal weights (Sec. 2.9).
  */
 #include <math.h>
 #include <pthread.h>
@@ -68,11 +73,14 @@ static inline uint64_t o_word(uint64_t K, uint64_t i, unsigned t) {
     uint64_t c = (i << 8) | (uint64_t)t;
     return o_mix64(K + (c + 1) * O_PHI);
 }
-/* Slots of point i.  Word 0 serves the point twice, drawing only the bits
- * each use needs (Sec. 3: random bits are consumed economically): its high 32
- * bits are the uniform behind the point value, its low 32 bits the label draw.
- * Words 1..8 hold Lemire redraws (low 32 bits); words 16..79 the rejection
- * pairs of the truncated-exponential sampler (53-bit uniforms). */
+/* Slots of point i.  Word 0 serves the point twice: its high 32 bits are the
+ * uniform behind the point value, its low 32 bits the label draw.  (The
+ * paper's implementation spends 53 random bits per uniform; with 32 the
+ * first-point values of ProbMinHash3/4 lie on a 2^-32 grid, so equal truncated
+ * values -- decided by position -- occur with probability about
+ * n / (m 2^32) per component.)  Words 1..8 hold Lemire redraws (low 32 bits);
+ * words 16..79 the proposal pairs of the truncated-exponential sampler (53-bit
+ * uniforms). */
 #define O_SLOT_POINT 0u
 #define O_SLOT_REDRAW 1u
 #define O_SLOT_REJ 16u
@@ -206,43 +214,66 @@ void or_log_table(double* out512) {
 /* Exp(1) by inversion; 0 - log(u) keeps the result +0 for u = 1. */
 static inline double o_exp1(uint64_t w) { return 0.0 - or_log_stream(o_upos(w)); }
 
-/* Uniform integer in [0, s), Lemire's multiply-and-reject method on the low
- * 32 bits of the point's word, redrawing from words 1..8 (at most 8 redraws). */
-static uint32_t o_lemire(uint64_t K, uint64_t i, uint32_t s) {
-    uint64_t x = o_word(K, i, O_SLOT_POINT) & 0xFFFFFFFFULL;
-    uint64_t prod = x * (uint64_t)s;
-    uint32_t lo = (uint32_t)prod;
-    if (lo < s) {
-        uint32_t thr = (uint32_t)(0u - s) % s;
-        for (unsigned r = 1; lo < thr && r <= 8; ++r) {
-            x = o_word(K, i, O_SLOT_REDRAW + r - 1) & 0xFFFFFFFFULL;
-            prod = x * (uint64_t)s;
-            lo = (uint32_t)prod;
-        }
-    }
+/* ------------------------------------------------------------------------ */
+/* Loop caps.  Sec. 3 advises bounding every loop of the generators; the caps
+ * are part of the definition of the result:
+ *   imax          points per element for the with-replacement variants
+ *                 ProbMinHash1/3 (default 6 m bitlen(m) + 64);
+ *   te_rounds     proposals of the truncated-exponential sampler's second
+ *                 branch (default 32, at most 32: word slots 16..79);
+ *   redraws       Lemire redraws (default 8, at most 8: word slots 1..8);
+ *   lemire_floor  validation only: draws whose low product half lies below
+ *                 max(threshold, floor) are redrawn too, which forces the
+ *                 redraw path (labels are then not uniform); default 0. */
+typedef struct {
+    uint64_t imax;
+    unsigned te_rounds;
+    unsigned redraws;
+    uint32_t lemire_floor;
+} o_caps;
+
+#define O_TE_ROUNDS_MAX 32u
+#define O_REDRAWS_MAX 8u
+
+/* Uniform integer in [0, s) by Lemire's multiply-shift: the product of s and
+ * the low 32 bits of the point's word; its high half is the draw, and its low
+ * half decides rejection (below (2^32 - s) mod s the draw is biased and the
+ * next word of slots 1..8 is tried). */
+static uint32_t o_lemire(const o_caps *C, uint64_t K, uint64_t i, uint32_t s) {
+    uint32_t thr = (uint32_t)(0u - s) % s;
+    if (thr < C->lemire_floor) thr = C->lemire_floor;
+    uint64_t prod = (o_word(K, i, O_SLOT_POINT) & 0xFFFFFFFFULL) * (uint64_t)s;
+    for (unsigned r = 1; r <= C->redraws && (uint32_t)prod < thr; ++r)
+        prod = (o_word(K, i, O_SLOT_REDRAW + r - 1) & 0xFFFFFFFFULL) * (uint64_t)s;
     return (uint32_t)(prod >> 32);
 }
 
-/* Truncated exponential Exp(lam; 0, 1) of Sec. 2.8 (area split into a
- * rectangle under e^-lam, then rejection from a triangle via a half-height
- * rectangle with reflection, two tangent tests and a final exact test).
- * c1 = (e^lam - 1)/lam, c2 = log(2/(1+e^-lam))/lam, c3 = (1-e^-lam)/lam.
- * The rejection loop is capped at 32 rounds (Sec. 3 recommends capped loops). */
-static double o_te(uint64_t K, uint64_t i, double lam, double c1, double c2, double c3) {
+/* Truncated exponential Exp(lam; 0, 1) of Sec. 2.8: density
+ * f(x) = lam e^(-lam x) / (1 - e^(-lam)) on [0, 1).  The scheme below is
+ * derived from f.  Let a = e^lam - 1 and c1 = a / lam.
+ *   1. f is smallest at x -> 1, where it equals lam / a = 1 / c1, so f is the
+ *      mixture of the uniform law (weight 1/c1) and a remainder.  x = c1 U
+ *      with U uniform in [0, 1) lies below 1 with probability 1/c1 and is then
+ *      uniform on [0, 1): that draw is the uniform part.
+ *   2. The remainder is proportional to e^(-lam x) - e^(-lam), i.e. to
+ *      g(t) = expm1(lam t) with t = 1 - x.  g is convex with g(0) = 0 and
+ *      g(1) = a, so a uniform point (x, v) of [0,1)^2 is accepted when
+ *      v a <= g(t).  Two bounds decide most proposals without evaluating g:
+ *      g(t) >= lam t (tangent at 0) accepts when v c1 <= t, and g(t) <= a t
+ *      (chord) rejects when v >= t.
+ * Step 1 uses the high 32 bits of the point's word (its low half is the label
+ * draw); the proposals of step 2 use 53-bit uniforms from slot pairs
+ * (16 + 2r, 17 + 2r), r < te_rounds; after the last rejected proposal its x is
+ * returned. */
+static double o_te(const o_caps *C, uint64_t K, uint64_t i, double lam, double a, double c1) {
     double x = c1 * o_u32(o_word(K, i, O_SLOT_POINT));
     if (x < 1.0) return x;
-    for (unsigned it = 0; it < 32; ++it) {
-        x = o_u53(o_word(K, i, O_SLOT_REJ + 2 * it));
-        if (x < c2) return x;
-        double y = 0.5 * o_u53(o_word(K, i, O_SLOT_REJ + 2 * it + 1));
-        if (y > 1.0 - x) {
-            x = 1.0 - x;
-            y = 1.0 - y;
-        }
-        if (x <= c3 * (1.0 - y)) return x;
-        double yc = y * c1;
-        if (yc <= 1.0 - x) return x;
-        if (yc * lam <= or_expm1(lam * (1.0 - x))) return x;
+    for (unsigned r = 0; r < C->te_rounds; ++r) {
+        x = o_u53(o_word(K, i, O_SLOT_REJ + 2 * r));
+        const double v = o_u53(o_word(K, i, O_SLOT_REJ + 2 * r + 1));
+        const double t = 1.0 - x;
+        if (v * c1 <= t) return x;
+        if (v < t && v * a <= or_expm1(lam * t)) return x;
     }
     return x;
 }
@@ -260,10 +291,10 @@ static inline uint64_t o_key(double x, uint32_t p) {
 typedef struct {
     int variant;
     uint32_t m;
-    uint64_t imax;  /* stream length cap for sampling with replacement */
-    double *beta;   /* PMH2: beta[i] = m/(m-i+1), i = 1..m */
-    double lam3, c1, c2, c3;       /* PMH3 */
-    double *lam4, *c14, *c24, *c34; /* PMH4, i = 1..m-1 */
+    o_caps caps;
+    double *beta;                   /* PMH2: beta[i] = m/(m-i+1), i = 1..m */
+    double lam3, a3, c13;           /* PMH3: lambda, e^lambda - 1, (e^lambda - 1)/lambda */
+    double *lam4, *a4, *c14;        /* PMH4, i = 1..m-1: the same for lambda_i */
     double *gam, *dgam;             /* PMH4: gamma[0..m-1], dgamma[1..m-1] */
     double delta;                   /* PMH4 */
     int binary;                     /* Sec. 2.9 specialisation (variants 5..8 = binary 1..4) */
@@ -278,12 +309,13 @@ static unsigned o_bitlen(uint32_t m) {
 uint64_t or_imax(uint32_t m) { return 6ULL * m * o_bitlen(m) + 64; }
 
 static void o_params_free(o_params *P) {
-    free(P->beta); free(P->lam4); free(P->c14); free(P->c24); free(P->c34);
+    free(P->beta); free(P->lam4); free(P->a4); free(P->c14);
     free(P->gam); free(P->dgam);
     memset(P, 0, sizeof(*P));
 }
 
-static int o_params_init(o_params *P, int variant, uint32_t m) {
+/* caps4 = {imax (0: default), te_rounds, redraws, lemire_floor} or NULL. */
+static int o_params_init(o_params *P, int variant, uint32_t m, const uint64_t *caps4) {
     memset(P, 0, sizeof(*P));
     /* Variants 5..8: ProbMinHash1..4 specialised to binary weights (Sec. 2.9,
      * "Conventional Jaccard Similarity"), called with unit weights.  PMH1/2
@@ -298,7 +330,19 @@ static int o_params_init(o_params *P, int variant, uint32_t m) {
     if ((variant == 3 || variant == 4) && m < 2) return O_ERR_VARIANT_M;
     P->variant = variant;
     P->m = m;
-    P->imax = or_imax(m);
+    P->caps.imax = or_imax(m);
+    P->caps.te_rounds = O_TE_ROUNDS_MAX;
+    P->caps.redraws = O_REDRAWS_MAX;
+    P->caps.lemire_floor = 0;
+    if (caps4) {
+        if (caps4[1] < 1 || caps4[1] > O_TE_ROUNDS_MAX || caps4[2] > O_REDRAWS_MAX ||
+            caps4[3] > 0xFFFFFFFFULL || caps4[0] > 0xFFFFFFFFULL)
+            return O_ERR_ARG;
+        if (caps4[0]) P->caps.imax = caps4[0];
+        P->caps.te_rounds = (unsigned)caps4[1];
+        P->caps.redraws = (unsigned)caps4[2];
+        P->caps.lemire_floor = (uint32_t)caps4[3];
+    }
     double dm = (double)m;
     if (variant == 2) {
         P->beta = malloc(sizeof(double) * (m + 1));
@@ -306,32 +350,26 @@ static int o_params_init(o_params *P, int variant, uint32_t m) {
         P->beta[0] = 0.0;
         for (uint32_t i = 1; i <= m; ++i) P->beta[i] = dm / (double)(m - i + 1);
     } else if (variant == 3) {
-        /* lambda = log(1 + 1/(m-1)); since e^lambda = m/(m-1) the sampler
-         * constants have closed forms in 1/(m-1), 1/(2m-1), 1/m. */
-        double a = 1.0 / (double)(m - 1);
-        P->lam3 = or_log1p(a);
-        P->c1 = a / P->lam3;
-        P->c2 = or_log1p(1.0 / (double)(2 * m - 1)) / P->lam3;
-        P->c3 = (1.0 / dm) / P->lam3;
+        /* lambda = log(1 + 1/(m-1)), so e^lambda - 1 = 1/(m-1) exactly */
+        P->a3 = 1.0 / (double)(m - 1);
+        P->lam3 = or_log1p(P->a3);
+        P->c13 = P->a3 / P->lam3;
     } else if (variant == 4) {
         P->lam4 = malloc(sizeof(double) * m);
+        P->a4 = malloc(sizeof(double) * m);
         P->c14 = malloc(sizeof(double) * m);
-        P->c24 = malloc(sizeof(double) * m);
-        P->c34 = malloc(sizeof(double) * m);
         P->gam = malloc(sizeof(double) * m);
         P->dgam = malloc(sizeof(double) * m);
-        if (!P->lam4 || !P->c14 || !P->c24 || !P->c34 || !P->gam || !P->dgam) {
+        if (!P->lam4 || !P->a4 || !P->c14 || !P->gam || !P->dgam) {
             o_params_free(P);
             return O_ERR_OOM;
         }
-        P->lam4[0] = P->c14[0] = P->c24[0] = P->c34[0] = 0.0;
+        P->lam4[0] = P->a4[0] = P->c14[0] = 0.0;
         for (uint32_t i = 1; i < m; ++i) {
-            double a = 1.0 / (double)(m - i);
-            double l = or_log1p(a); /* lambda_i = log(1 + 1/(m-i)) */
-            P->lam4[i] = l;
-            P->c14[i] = a / l;
-            P->c24[i] = or_log1p(1.0 / (double)(2 * (m - i) + 1)) / l;
-            P->c34[i] = (1.0 / (double)(m - i + 1)) / l;
+            /* lambda_i = log(1 + 1/(m-i)): e^lambda_i - 1 = 1/(m-i) */
+            P->a4[i] = 1.0 / (double)(m - i);
+            P->lam4[i] = or_log1p(P->a4[i]);
+            P->c14[i] = P->a4[i] / P->lam4[i];
         }
         P->gam[0] = 0.0;
         for (uint32_t i = 1; i < m; ++i)
@@ -346,9 +384,10 @@ static int o_params_init(o_params *P, int variant, uint32_t m) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Point streams.  Point i >= 1 of element K (weight inverse winv).  PMH1/PMH2
- * accumulate the exponential spacings in 64-bit fixed point (2^-32 units) and
- * round once: x_i = winv * (T_i 2^-32), T_i = T_{i-1} + floor(s_i 2^32). */
+/* Point streams (Sec. 2.1, 2.3-2.6).  Point i >= 1 of element K (weight
+ * inverse winv).  ProbMinHash1/2 accumulate the exponential spacings in
+ * 64-bit fixed point (2^-32 units) and round once:
+ * x_i = winv * (T_i 2^-32), T_i = T_{i-1} + floor(s_i 2^32). */
 static inline uint64_t o_spacing(const o_params *P, uint64_t K, uint64_t i) {
     double E = o_exp1(o_word(K, i, O_SLOT_POINT));
     if (P->variant == 2) E = P->beta[i] * E;
@@ -356,23 +395,36 @@ static inline uint64_t o_spacing(const o_params *P, uint64_t K, uint64_t i) {
 }
 static inline double o_fixed_value(double winv, uint64_t T) { return winv * ((double)T * 0x1p-32); }
 
+/* ProbMinHash3/4 place point i in an interval starting at o_lower(i) (Sec. 2.5,
+ * Sec. 2.6): winv (i-1), resp. winv gamma_{i-1}; the intervals increase with i. */
+static inline double o_lower(const o_params *P, double winv, uint64_t i) {
+    if (P->variant == 3) return winv * (double)(i - 1);
+    return winv * P->gam[i - 1];
+}
 static inline double o_value3(const o_params *P, uint64_t K, uint64_t i, double winv) {
     if (P->binary) return (double)(i - 1) + o_u32(o_word(K, i, O_SLOT_POINT));
     double lb = winv * (double)(i - 1);
-    return lb + winv * o_te(K, i, P->lam3, P->c1, P->c2, P->c3);
+    return lb + winv * o_te(&P->caps, K, i, P->lam3, P->a3, P->c13);
 }
 static inline double o_value4(const o_params *P, uint64_t K, uint64_t i, double winv) {
     uint32_t m = P->m;
     if (P->binary) return (double)(i - 1) + o_u32(o_word(K, i, O_SLOT_POINT));
     if (i < m)
-        return winv * (P->gam[i - 1] +
-                       P->dgam[i] * o_te(K, i, P->lam4[i], P->c14[i], P->c24[i], P->c34[i]));
+        return winv * (P->gam[i - 1] + P->dgam[i] * o_te(&P->caps, K, i, P->lam4[i], P->a4[i], P->c14[i]));
     return winv * (P->gam[m - 1] + P->delta * o_exp1(o_word(K, i, O_SLOT_POINT)));
 }
+/* Last point of a stream: the without-replacement variants draw every label
+ * once (Sec. 2.4, 2.6), the others stop at the cap. */
+static inline uint64_t o_stream_end(const o_params *P) {
+    return (P->variant == 2 || P->variant == 4) ? P->m : P->caps.imax;
+}
 
-/* Lazy Fisher-Yates permutation generator of Sec. 2.4 (arrays g, v and the
- * version counter c), 0-based positions.  Step i (1-based) draws
- * j = (i-1) + U{0..m-i}, returns g[j], moves g[i-1] into slot j. */
+/* Random permutation of the labels drawn one step at a time (Sec. 2.4: a
+ * Fisher-Yates shuffle whose array is initialised lazily, so a stream that
+ * stops early costs only its steps).  g[j] is valid where v[j] equals the
+ * current version c; elsewhere the slot still holds j.  Step i (1-based)
+ * draws slot j uniformly from i-1..m-1, yields the value of slot j and moves
+ * the value of slot i-1 into slot j. */
 typedef struct {
     uint32_t *g, *v;
     uint32_t c, i, m;
@@ -388,224 +440,146 @@ static int o_perm_init(o_perm *F, uint32_t m) {
 }
 static void o_perm_free(o_perm *F) { free(F->g); free(F->v); }
 static inline void o_perm_reset(o_perm *F) {
-    if (F->c == 0xFFFFFFFFu) { /* version counter wraps: forget old versions */
+    if (F->c == 0xFFFFFFFFu) { /* the version counter would wrap: clear the versions */
         memset(F->v, 0, sizeof(uint32_t) * F->m);
         F->c = 0;
     }
     F->i = 0;
     F->c += 1;
 }
-static inline uint32_t o_perm_next(o_perm *F, uint64_t K) {
-    F->i += 1;
-    uint32_t i = F->i;
-    uint32_t j = (i - 1) + o_lemire(K, i, F->m - i + 1);
-    uint32_t k = (F->v[j] == F->c) ? F->g[j] : j;
-    F->g[j] = (F->v[i - 1] == F->c) ? F->g[i - 1] : (i - 1);
+static inline uint32_t o_perm_slot(const o_perm *F, uint32_t j) { return F->v[j] == F->c ? F->g[j] : j; }
+static inline uint32_t o_perm_next(const o_caps *C, o_perm *F, uint64_t K) {
+    const uint32_t i = ++F->i;
+    const uint32_t j = (i - 1) + o_lemire(C, K, i, F->m - i + 1);
+    const uint32_t out = o_perm_slot(F, j);
+    F->g[j] = o_perm_slot(F, i - 1);
     F->v[j] = F->c;
-    return k;
+    return out;
 }
 
 /* ------------------------------------------------------------------------ */
-/* Stop-limit tree of Sec. 2.2 over keys: q[1..m] leaves, q[m+1..2m-1] inner
- * nodes, parent of k is m + ceil(k/2), root q[2m-1] = max_k q[k]. */
-static inline void o_tree_update(uint64_t *q, uint32_t m, uint32_t k1, uint64_t h) {
-    uint64_t k = k1; /* 1-based */
-    while (h < q[k]) {
-        q[k] = h;
-        uint64_t i = m + (k + 1) / 2;
-        if (i >= 2ULL * m) break;
-        uint64_t j = ((k - 1) ^ 1ULL) + 1;
-        if (q[j] >= q[i]) break;
-        if (h < q[j]) h = q[j];
-        k = i;
-    }
-}
-
+/* Signature under construction: keys[k] = the smallest key offered to
+ * component k so far (eq. (1) in key space), and the stop limit kmax =
+ * max_k keys[k] (Sec. 2: no point at or above it can change the signature).
+ * kmax stays EMPTY while some component is empty and is recomputed by a scan
+ * when the component holding it is lowered. */
 typedef struct {
+    uint64_t *keys;
+    uint32_t m;
+    uint32_t empty;  /* components still EMPTY */
+    uint64_t kmax;
     uint64_t points; /* points generated */
     uint64_t labels; /* labels drawn */
-    uint64_t buffer; /* interleaved: elements in the buffer after the first pass (its maximum) */
-} o_stats;
+} o_sig;
 
-static inline uint64_t o_elem_key(uint64_t seedhash, uint64_t id) { return o_mix64(id ^ seedhash); }
+static void o_sig_reset(o_sig *S) {
+    for (uint32_t k = 0; k < S->m; ++k) S->keys[k] = O_EMPTY;
+    S->empty = S->m;
+    S->kmax = O_EMPTY;
+}
+static void o_offer(o_sig *S, uint32_t k, uint64_t key) {
+    const uint64_t old = S->keys[k];
+    if (key >= old) return;
+    S->keys[k] = key;
+    if (old == O_EMPTY) {
+        if (--S->empty > 0) return;
+    } else if (old != S->kmax) {
+        return;
+    }
+    uint64_t mx = 0;
+    for (uint32_t j = 0; j < S->m; ++j) mx = S->keys[j] > mx ? S->keys[j] : mx;
+    S->kmax = mx;
+}
 
-/* Sequential ProbMinHash over one set.  q has 2m entries (index 0 unused). */
+/* One element's stream as it is consumed point by point. */
+typedef struct {
+    uint32_t p;     /* position in the set (the key's tie-break) */
+    double winv;
+    uint64_t K;
+    uint64_t i;     /* next point */
+    uint64_t T;     /* ProbMinHash1/2: fixed-point sum through point i-1 */
+    double x;       /* value of point i-1 */
+} o_elem;
+
+static inline o_elem o_elem_start(uint64_t seedhash, uint64_t id, double w, uint32_t p) {
+    o_elem e = {p, 1.0 / w, o_mix64(id ^ seedhash), 1, 0, 0.0};
+    return e;
+}
+
+/* Consumes point i of the element unless a lower bound of the values of
+ * points i, i+1, ... reaches the stop limit; offers the point to its label.
+ * Returns 1 while a later point may still lower a component.  Lower bounds:
+ * the exponential-spacing streams (ProbMinHash1/2) increase, so the previous
+ * point bounds the next ones and a point bounds itself; the interval streams
+ * (ProbMinHash3/4) are bounded by the start of the point's interval.  F: the
+ * element's permutation (ProbMinHash2/4). */
+static int o_step(const o_params *P, o_elem *e, o_perm *F, o_sig *S) {
+    const uint64_t i = e->i;
+    const int expo = P->variant <= 2;
+    double x;
+    if (expo) {
+        if (i > 1 && o_key(e->x, e->p) >= S->kmax) return 0;
+        e->T += o_spacing(P, e->K, i);
+        x = o_fixed_value(e->winv, e->T);
+        S->points++;
+        if (o_key(x, e->p) >= S->kmax) return 0;
+    } else {
+        if (o_key(o_lower(P, e->winv, i), e->p) >= S->kmax) return 0;
+        x = P->variant == 3 ? o_value3(P, e->K, i, e->winv) : o_value4(P, e->K, i, e->winv);
+        S->points++;
+    }
+    const uint64_t key = o_key(x, e->p);
+    if (P->variant == 2 || P->variant == 4) { /* every generated point takes its permutation step */
+        S->labels++;
+        o_offer(S, o_perm_next(&P->caps, F, e->K), key);
+    } else if (key < S->kmax) {
+        S->labels++;
+        o_offer(S, o_lemire(&P->caps, e->K, i, P->m), key);
+    }
+    e->x = x;
+    e->i = i + 1;
+    if (i == o_stream_end(P)) return 0;
+    if (expo) return o_key(x, e->p) < S->kmax;
+    return o_key(o_lower(P, e->winv, i + 1), e->p) < S->kmax;
+}
+
+/* Sequential signature (Sec. 2.3-2.6): each element's stream in turn, until
+ * it can no longer lower a component. */
 static void o_sign_seq(const o_params *P, uint64_t seedhash, const uint64_t *ids, const double *w,
-                       uint32_t n, uint64_t *q, o_perm *F, o_stats *st) {
-    const uint32_t m = P->m;
-    const uint64_t root = 2ULL * m - 1;
-    for (uint64_t k = 1; k <= root; ++k) q[k] = O_EMPTY;
+                       uint32_t n, o_sig *S, o_perm *F) {
+    o_sig_reset(S);
     for (uint32_t p = 0; p < n; ++p) {
         if (!(w[p] > 0.0)) continue;
-        const double winv = 1.0 / w[p];
-        const uint64_t K = o_elem_key(seedhash, ids[p]);
-        if (P->variant == 1) { /* ProbMinHash1, Sec. 2.3 */
-            uint64_t i = 1, T = o_spacing(P, K, 1);
-            double h = o_fixed_value(winv, T);
-            st->points++;
-            while (o_key(h, p) < q[root]) {
-                uint32_t k = o_lemire(K, i, m);
-                st->labels++;
-                uint64_t key = o_key(h, p);
-                if (key < q[k + 1]) {
-                    o_tree_update(q, m, k + 1, key);
-                    if (key >= q[root]) break;
-                }
-                if (i == P->imax) break;
-                ++i;
-                T += o_spacing(P, K, i);
-                h = o_fixed_value(winv, T);
-                st->points++;
-            }
-        } else if (P->variant == 2) { /* ProbMinHash2, Sec. 2.4 */
-            o_perm_reset(F);
-            uint64_t i = 1, T = o_spacing(P, K, 1);
-            double h = o_fixed_value(winv, T);
-            st->points++;
-            while (o_key(h, p) < q[root]) {
-                uint32_t k = o_perm_next(F, K);
-                st->labels++;
-                uint64_t key = o_key(h, p);
-                if (key < q[k + 1]) {
-                    o_tree_update(q, m, k + 1, key);
-                    if (key >= q[root]) break;
-                }
-                if (i == m) break; /* the permutation is exhausted */
-                ++i;
-                T += o_spacing(P, K, i);
-                h = o_fixed_value(winv, T);
-                st->points++;
-            }
-        } else if (P->variant == 3) { /* ProbMinHash3, Sec. 2.5 */
-            uint64_t i = 1;
-            double h = o_value3(P, K, 1, winv);
-            st->points++;
-            for (;;) {
-                uint64_t key = o_key(h, p);
-                if (key < q[root]) {
-                    uint32_t k = o_lemire(K, i, m);
-                    st->labels++;
-                    if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
-                }
-                if (i == P->imax) break;
-                ++i;
-                /* point i lies in [winv (i-1), winv i): stop on the lower bound */
-                if (o_key(winv * (double)(i - 1), p) >= q[root]) break;
-                h = o_value3(P, K, i, winv);
-                st->points++;
-            }
-        } else { /* ProbMinHash4, Sec. 2.6 */
-            o_perm_reset(F);
-            uint64_t i = 1;
-            double h = o_value4(P, K, 1, winv);
-            st->points++;
-            for (;;) {
-                /* every generated point takes its Fisher-Yates step so the
-                 * label of the next point is defined */
-                uint32_t k = o_perm_next(F, K);
-                st->labels++;
-                uint64_t key = o_key(h, p);
-                if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
-                if (i == m) break;
-                ++i;
-                if (o_key(winv * P->gam[i - 1], p) >= q[root]) break;
-                h = o_value4(P, K, i, winv);
-                st->points++;
-            }
+        o_elem e = o_elem_start(seedhash, ids[p], w[p], p);
+        o_perm_reset(F);
+        while (o_step(P, &e, F, S)) {
         }
     }
 }
 
-/* Interleaved ProbMinHash1a / ProbMinHash3a of Sec. 2.7: first points of all
- * elements in one pass, then repeated passes over a buffer of live elements. */
-typedef struct {
-    uint32_t p;
-    double winv;
-    uint64_t K;
-    uint64_t i; /* index of the last generated point */
-    uint64_t T; /* PMH1 fixed-point accumulator */
-    double h;
-} o_live;
-
+/* Interleaved ProbMinHash1a / ProbMinHash3a (Sec. 2.7): one point of every
+ * element, then passes over the elements that can still lower a component,
+ * one point each, until none is left.  *buffer receives the number of live
+ * elements after the first pass (the largest the buffer gets). */
 static int o_sign_interleaved(const o_params *P, uint64_t seedhash, const uint64_t *ids,
-                              const double *w, uint32_t n, uint64_t *q, o_stats *st) {
-    const uint32_t m = P->m;
-    const uint64_t root = 2ULL * m - 1;
-    for (uint64_t k = 1; k <= root; ++k) q[k] = O_EMPTY;
-    o_live *buf = malloc(sizeof(o_live) * (n ? n : 1));
-    if (!buf) return O_ERR_OOM;
+                              const double *w, uint32_t n, o_sig *S, uint64_t *buffer) {
+    o_sig_reset(S);
+    o_elem *live = malloc(sizeof(o_elem) * (n ? n : 1));
+    if (!live) return O_ERR_OOM;
     uint32_t s = 0;
     for (uint32_t p = 0; p < n; ++p) {
         if (!(w[p] > 0.0)) continue;
-        double winv = 1.0 / w[p];
-        uint64_t K = o_elem_key(seedhash, ids[p]);
-        if (P->variant == 1) {
-            uint64_t T = o_spacing(P, K, 1);
-            double h = o_fixed_value(winv, T);
-            st->points++;
-            uint64_t key = o_key(h, p);
-            if (key >= q[root]) continue;
-            uint32_t k = o_lemire(K, 1, m);
-            st->labels++;
-            if (key < q[k + 1]) {
-                o_tree_update(q, m, k + 1, key);
-                if (key >= q[root]) continue;
-            }
-            if (P->imax == 1) continue;
-            buf[s++] = (o_live){p, winv, K, 1, T, h};
-        } else {
-            double h = o_value3(P, K, 1, winv);
-            st->points++;
-            uint64_t key = o_key(h, p);
-            if (key < q[root]) {
-                uint32_t k = o_lemire(K, 1, m);
-                st->labels++;
-                if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
-            }
-            if (o_key(winv, p) >= q[root] || P->imax == 1) continue;
-            buf[s++] = (o_live){p, winv, K, 1, 0, h};
-        }
+        o_elem e = o_elem_start(seedhash, ids[p], w[p], p);
+        if (o_step(P, &e, NULL, S)) live[s++] = e;
     }
-    st->buffer = s; /* the buffer only shrinks from here (Sec. 2.7 space analysis) */
+    *buffer = s;
     while (s > 0) {
         uint32_t t = 0;
-        for (uint32_t j = 0; j < s; ++j) {
-            o_live e = buf[j];
-            if (P->variant == 1) {
-                if (o_key(e.h, e.p) >= q[root]) continue;
-                e.i += 1;
-                e.T += o_spacing(P, e.K, e.i);
-                e.h = o_fixed_value(e.winv, e.T);
-                st->points++;
-                uint64_t key = o_key(e.h, e.p);
-                if (key >= q[root]) continue;
-                uint32_t k = o_lemire(e.K, e.i, m);
-                st->labels++;
-                if (key < q[k + 1]) {
-                    o_tree_update(q, m, k + 1, key);
-                    if (key >= q[root]) continue;
-                }
-                if (e.i == P->imax) continue;
-            } else {
-                e.i += 1;
-                double lb = e.winv * (double)(e.i - 1);
-                if (o_key(lb, e.p) >= q[root]) continue;
-                e.h = o_value3(P, e.K, e.i, e.winv);
-                st->points++;
-                uint64_t key = o_key(e.h, e.p);
-                if (key < q[root]) {
-                    uint32_t k = o_lemire(e.K, e.i, m);
-                    st->labels++;
-                    if (key < q[k + 1]) o_tree_update(q, m, k + 1, key);
-                }
-                if (e.i == P->imax) continue;
-                if (o_key(e.winv * (double)e.i, e.p) >= q[root]) continue;
-            }
-            buf[t++] = e;
-        }
+        for (uint32_t j = 0; j < s; ++j)
+            if (o_step(P, &live[j], NULL, S)) live[t++] = live[j];
         s = t;
     }
-    free(buf);
+    free(live);
     return O_OK;
 }
 
@@ -613,16 +587,16 @@ static int o_sign_interleaved(const o_params *P, uint64_t seedhash, const uint64
  * permutation for PMH2/4, to the cap for PMH1/3), then key_k = min over all
  * points labelled k.  No stop rule is involved. */
 static int o_sign_brute(const o_params *P, uint64_t seedhash, const uint64_t *ids, const double *w,
-                        uint32_t n, uint64_t *keys, o_stats *st) {
+                        uint32_t n, uint64_t *keys, uint64_t *points) {
     const uint32_t m = P->m;
     o_perm F;
     if (o_perm_init(&F, m) != O_OK) { o_perm_free(&F); return O_ERR_OOM; }
     for (uint32_t k = 0; k < m; ++k) keys[k] = O_EMPTY;
-    const uint64_t last = (P->variant == 2 || P->variant == 4) ? m : P->imax;
+    const uint64_t last = o_stream_end(P);
     for (uint32_t p = 0; p < n; ++p) {
         if (!(w[p] > 0.0)) continue;
         double winv = 1.0 / w[p];
-        uint64_t K = o_elem_key(seedhash, ids[p]);
+        uint64_t K = o_mix64(ids[p] ^ seedhash);
         uint64_t T = 0;
         o_perm_reset(&F);
         for (uint64_t i = 1; i <= last; ++i) {
@@ -636,9 +610,9 @@ static int o_sign_brute(const o_params *P, uint64_t seedhash, const uint64_t *id
             } else {
                 x = o_value4(P, K, i, winv);
             }
-            if (P->variant == 1 || P->variant == 3) k = o_lemire(K, i, m);
-            else k = o_perm_next(&F, K);
-            st->points++;
+            if (P->variant == 1 || P->variant == 3) k = o_lemire(&P->caps, K, i, m);
+            else k = o_perm_next(&P->caps, &F, K);
+            (*points)++;
             uint64_t key = o_key(x, p);
             if (key < keys[k]) keys[k] = key;
         }
@@ -663,42 +637,50 @@ uint64_t or_seedhash(uint64_t seed) { return o_mix64(seed); }
 uint64_t or_mix64(uint64_t z) { return o_mix64(z); }
 uint64_t or_word(uint64_t K, uint64_t i, unsigned t) { return o_word(K, i, t); }
 double or_exp1_word(uint64_t w) { return o_exp1(w); }
-uint32_t or_lemire(uint64_t K, uint64_t i, uint32_t s) { return o_lemire(K, i, s); }
-double or_te(uint64_t K, uint64_t i, double lam, double c1, double c2, double c3) {
-    return o_te(K, i, lam, c1, c2, c3);
+/* Lemire draw from [0, s) of point i with redraws <= 8 and a validation floor. */
+uint32_t or_lemire(uint64_t K, uint64_t i, uint32_t s, unsigned redraws, uint32_t floor) {
+    o_caps C = {0, O_TE_ROUNDS_MAX, redraws > O_REDRAWS_MAX ? O_REDRAWS_MAX : redraws, floor};
+    return o_lemire(&C, K, i, s);
+}
+/* Truncated exponential of point i (rate lam, a = e^lam - 1, c1 = a/lam) with
+ * at most rounds (1..32) proposals in the second branch. */
+double or_te(uint64_t K, uint64_t i, double lam, double a, double c1, unsigned rounds) {
+    o_caps C = {0, rounds < 1 ? 1 : (rounds > O_TE_ROUNDS_MAX ? O_TE_ROUNDS_MAX : rounds), O_REDRAWS_MAX, 0};
+    return o_te(&C, K, i, lam, a, c1);
 }
 uint64_t or_key(double x, uint32_t p) { return o_key(x, p); }
 
 /* Constants of (variant, m) for inspection by the tests.  out[] receives
- * PMH3: {lambda, c1, c2, c3}; PMH4 with index i: {lambda_i, c1_i, c2_i, c3_i,
- * gamma_i, dgamma_i, delta}; PMH2 with index i: {beta_i}. */
+ * PMH3: {lambda, a = e^lambda - 1, c1 = a/lambda}; PMH4 with index i:
+ * {lambda_i, a_i, c1_i, gamma_i, dgamma_i, delta}; PMH2 with index i:
+ * {beta_i}. */
 int or_constants(int variant, uint32_t m, uint32_t i, double *out) {
     o_params P;
-    int rc = o_params_init(&P, variant, m);
+    int rc = o_params_init(&P, variant, m, NULL);
     if (rc) return rc;
     if (P.variant == 2 && i >= 1 && i <= m) out[0] = P.beta[i];
-    if (P.variant == 3) { out[0] = P.lam3; out[1] = P.c1; out[2] = P.c2; out[3] = P.c3; }
+    if (P.variant == 3) { out[0] = P.lam3; out[1] = P.a3; out[2] = P.c13; }
     if (P.variant == 4 && i < m) {
-        out[0] = P.lam4[i]; out[1] = P.c14[i]; out[2] = P.c24[i]; out[3] = P.c34[i];
-        out[4] = P.gam[i]; out[5] = P.dgam[i]; out[6] = P.delta;
+        out[0] = P.lam4[i]; out[1] = P.a4[i]; out[2] = P.c14[i];
+        out[3] = P.gam[i]; out[4] = P.dgam[i]; out[5] = P.delta;
     }
     o_params_free(&P);
     return O_OK;
 }
 
-/* Point i of element K with weight inverse winv, for stream tests: value and
- * label of points 1..count written to xs/ls (labels by Lemire for PMH1/3, by
- * the Fisher-Yates steps 1..count for PMH2/4). */
+/* Points 1..count of element K with weight inverse winv, for stream tests:
+ * values and labels written to xs/ls (labels by Lemire for PMH1/3, by the
+ * permutation steps 1..count for PMH2/4).  caps4 as for or_sign_capped. */
 int or_stream(int variant, uint32_t m, uint64_t K, double winv, uint64_t count, double *xs,
-              uint32_t *ls) {
+              uint32_t *ls, const uint64_t *caps4) {
     o_params P;
-    int rc = o_params_init(&P, variant, m);
+    int rc = o_params_init(&P, variant, m, caps4);
     if (rc) return rc;
     o_perm F;
     if (o_perm_init(&F, m) != O_OK) { o_perm_free(&F); o_params_free(&P); return O_ERR_OOM; }
     o_perm_reset(&F);
     uint64_t T = 0;
-    uint64_t last = (P.variant == 2 || P.variant == 4) ? m : P.imax;
+    const uint64_t last = o_stream_end(&P);
     for (uint64_t i = 1; i <= count && i <= last; ++i) {
         if (P.variant <= 2) {
             T += o_spacing(&P, K, i);
@@ -708,7 +690,7 @@ int or_stream(int variant, uint32_t m, uint64_t K, double winv, uint64_t count, 
         } else {
             xs[i - 1] = o_value4(&P, K, i, winv);
         }
-        ls[i - 1] = (P.variant == 1 || P.variant == 3) ? o_lemire(K, i, m) : o_perm_next(&F, K);
+        ls[i - 1] = (P.variant == 1 || P.variant == 3) ? o_lemire(&P.caps, K, i, m) : o_perm_next(&P.caps, &F, K);
     }
     o_perm_free(&F);
     o_params_free(&P);
@@ -717,35 +699,42 @@ int or_stream(int variant, uint32_t m, uint64_t K, double winv, uint64_t count, 
 
 /* mode 0: sequential (Sec. 2.3-2.6), 1: interleaved (Sec. 2.7, PMH1/PMH3
  * only), 2: brute force.  keys[m] out; stats[3] = {points, labels, buffer
- * size after the first pass (interleaved mode, else 0)}. */
-int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
-            uint64_t n, uint64_t *keys, uint64_t *stats) {
+ * size after the first pass (interleaved mode, else 0)}.  caps4 = {imax (0:
+ * default), te_rounds (1..32), redraws (0..8), lemire_floor} or NULL for the
+ * default caps. */
+int or_sign_capped(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+                   uint64_t n, uint64_t *keys, uint64_t *stats, const uint64_t *caps4) {
     if ((!ids || !w) && n) return O_ERR_ARG;
     if (n > O_MAX_SET) return O_ERR_SET_TOO_LARGE;
     int rc = o_check_weights(w, n);
     if (rc) return rc;
     o_params P;
-    rc = o_params_init(&P, variant, m);
+    rc = o_params_init(&P, variant, m, caps4);
     if (rc) return rc;
     if (mode == 1 && P.variant != 1 && P.variant != 3) { o_params_free(&P); return O_ERR_ARG; }
-    uint64_t sh = o_mix64(seed);
-    o_stats st = {0, 0, 0};
+    const uint64_t sh = o_mix64(seed);
+    uint64_t points = 0, labels = 0, buffer = 0;
     if (mode == 2) {
-        rc = o_sign_brute(&P, sh, ids, w, (uint32_t)n, keys, &st);
+        rc = o_sign_brute(&P, sh, ids, w, (uint32_t)n, keys, &points);
     } else {
-        uint64_t *q = malloc(sizeof(uint64_t) * 2 * m);
+        o_sig S = {keys, m, 0, 0, 0, 0};
         o_perm F;
         rc = o_perm_init(&F, m);
-        if (!q || rc) rc = O_ERR_OOM;
-        else if (mode == 0) o_sign_seq(&P, sh, ids, w, (uint32_t)n, q, &F, &st);
-        else rc = o_sign_interleaved(&P, sh, ids, w, (uint32_t)n, q, &st);
-        if (!rc) memcpy(keys, q + 1, sizeof(uint64_t) * m);
-        free(q);
+        if (rc) rc = O_ERR_OOM;
+        else if (mode == 0) o_sign_seq(&P, sh, ids, w, (uint32_t)n, &S, &F);
+        else rc = o_sign_interleaved(&P, sh, ids, w, (uint32_t)n, &S, &buffer);
         o_perm_free(&F);
+        points = S.points;
+        labels = S.labels;
     }
-    if (stats) { stats[0] = st.points; stats[1] = st.labels; stats[2] = st.buffer; }
+    if (stats) { stats[0] = points; stats[1] = labels; stats[2] = buffer; }
     o_params_free(&P);
     return rc;
+}
+
+int or_sign(int mode, int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+            uint64_t n, uint64_t *keys, uint64_t *stats) {
+    return or_sign_capped(mode, variant, seed, m, ids, w, n, keys, stats, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -763,7 +752,7 @@ static void o_pminhash(uint64_t sh, const uint64_t *ids, const double *w, uint32
     for (uint32_t p = 0; p < n; ++p) {
         if (w[p] == 0.0) continue;
         const double winv = 1.0 / w[p];
-        const uint64_t K = o_elem_key(sh, ids[p]);
+        const uint64_t K = o_mix64(ids[p] ^ sh);
         for (uint32_t k = 1; k <= m; ++k) {
             const uint64_t key = o_key(winv * o_exp1(o_word(K, k, O_SLOT_PMIN)), p);
             if (key < keys[k - 1]) keys[k - 1] = key;
@@ -860,18 +849,19 @@ typedef struct {
 static void *o_batch_worker(void *arg) {
     o_batch *B = arg;
     const uint32_t m = B->P ? B->P->m : B->pm;
-    uint64_t *q = malloc(sizeof(uint64_t) * 2 * m);
     o_perm F;
     int rc = o_perm_init(&F, m);
-    o_stats st = {0, 0, 0};
-    if (q && !rc) {
+    uint64_t points = 0, labels = 0;
+    if (!rc) {
         for (;;) {
             uint64_t s = __atomic_fetch_add(&B->next, 1, __ATOMIC_RELAXED);
             if (s >= B->num_sets) break;
             uint64_t a = B->off[s], b = B->off[s + 1];
             if (B->P) {
-                o_sign_seq(B->P, B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), q, &F, &st);
-                memcpy(B->keys + s * m, q + 1, sizeof(uint64_t) * m);
+                o_sig S = {B->keys + s * m, m, 0, 0, 0, 0};
+                o_sign_seq(B->P, B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), &S, &F);
+                points += S.points;
+                labels += S.labels;
             } else {
                 o_pminhash(B->sh, B->ids + a, B->w + a, (uint32_t)(b - a), m, B->keys + s * m);
             }
@@ -880,18 +870,17 @@ static void *o_batch_worker(void *arg) {
         rc = O_ERR_OOM;
     }
     pthread_mutex_lock(&B->lock);
-    B->points += st.points;
-    B->labels += st.labels;
+    B->points += points;
+    B->labels += labels;
     if (rc) B->rc = rc;
     pthread_mutex_unlock(&B->lock);
-    free(q);
     o_perm_free(&F);
     return NULL;
 }
 
-int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
-                  const uint64_t *offsets, uint64_t num_sets, uint64_t *keys_out, int nthreads,
-                  uint64_t *stats) {
+int or_sign_batch_capped(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+                         const uint64_t *offsets, uint64_t num_sets, uint64_t *keys_out, int nthreads,
+                         uint64_t *stats, const uint64_t *caps4) {
     if (!offsets || !keys_out) return O_ERR_ARG;
     if (offsets[0] != 0) return O_ERR_ARG;
     for (uint64_t s = 0; s < num_sets; ++s) {
@@ -901,7 +890,7 @@ int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, c
     int rc = o_check_weights(w, offsets[num_sets]);
     if (rc) return rc;
     o_params P;
-    rc = o_params_init(&P, variant, m);
+    rc = o_params_init(&P, variant, m, caps4);
     if (rc) return rc;
     o_batch B = {&P, m, o_mix64(seed), ids, w, offsets, num_sets, keys_out, 0,
                  PTHREAD_MUTEX_INITIALIZER, 0, 0, 0};
@@ -916,6 +905,12 @@ int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, c
     if (stats) { stats[0] = B.points; stats[1] = B.labels; }
     o_params_free(&P);
     return B.rc;
+}
+
+int or_sign_batch(int variant, uint64_t seed, uint32_t m, const uint64_t *ids, const double *w,
+                  const uint64_t *offsets, uint64_t num_sets, uint64_t *keys_out, int nthreads,
+                  uint64_t *stats) {
+    return or_sign_batch_capped(variant, seed, m, ids, w, offsets, num_sets, keys_out, nthreads, stats, NULL);
 }
 
 /* P-MinHash over a batch of sets in CSR form (keys_out: num_sets * m). */

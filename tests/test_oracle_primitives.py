@@ -84,6 +84,22 @@ def test_expm1_accuracy(oracle):
     assert oracle.spec_expm1(0.0) == 0.0
 
 
+def test_word_stream_against_published_splitmix64(oracle):
+    """The word stream's first words from key 1234567 are the published
+    SplitMix64 outputs from that seed: this pins the mix constants, the
+    golden-ratio increment and the counter addressing (tests/golden/
+    splitmix64_reference.json names the source)."""
+    gold = json.load(open(os.path.join(os.path.dirname(GOLDEN), "splitmix64_reference.json")))
+    K = gold["seed"]
+    want = [int(v) for v in gold["outputs"]]
+    assert [oracle.word(K, 0, t) for t in range(len(want))] == want
+    # counter c = (i << 8) | t: point 1 slot 0 is output 257 of the generator
+    z = K
+    for _ in range(257):
+        z = (z + 0x9E3779B97F4A7C15) & (2**64 - 1)
+    assert oracle.word(K, 1, 0) == oracle.mix64(z)
+
+
 def test_mix64_is_a_bijection_step(oracle):
     """The SplitMix64 output function is a composition of invertible steps
     (xor-shift by >= 27 bits, multiplication by odd constants): invert it with
@@ -147,6 +163,28 @@ def test_lemire_uniform(oracle):
             assert stats.kstest(draws / s, "uniform").pvalue > 1e-3
 
 
+def test_lemire_redraw_path_and_cap(oracle):
+    """Lemire's rejection (a biased low product half is redrawn from the next
+    slot) and its cap of 8 redraws (Sec. 3 bounds every loop), forced with the
+    validation floor: the label equals the one computed here from the words."""
+    K, s = 31337, 1000
+    for floor in (1 << 31, (1 << 32) - 1):
+        for redraws in (0, 1, 3, 8):
+            for i in range(1, 200):
+                want = None
+                thr = max((2**32 - s) % s, floor)
+                prod = (oracle.word(K, i, 0) & 0xFFFFFFFF) * s
+                r = 1
+                while r <= redraws and (prod & 0xFFFFFFFF) < thr:
+                    prod = (oracle.word(K, i, r) & 0xFFFFFFFF) * s
+                    r += 1
+                want = prod >> 32
+                assert oracle.lemire(K, i, s, redraws, floor) == want
+    # without the floor the default threshold leaves these draws alone
+    assert all(oracle.lemire(K, i, s) == ((oracle.word(K, i, 0) & 0xFFFFFFFF) * s) >> 32 or
+               ((oracle.word(K, i, 0) & 0xFFFFFFFF) * s) & 0xFFFFFFFF < (2**32 - s) % s for i in range(1, 2000))
+
+
 def _te_cdf(lam):
     return lambda x: (1 - np.exp(-lam * x)) / (1 - math.exp(-lam))
 
@@ -154,21 +192,63 @@ def _te_cdf(lam):
 @pytest.mark.parametrize("m", [2, 4, 16, 256, 4096])
 def test_truncated_exponential_law(oracle, m):
     """Exp(lambda; 0, 1) of Sec. 2.8 has CDF (1 - e^{-lambda x})/(1 - e^{-lambda})."""
-    lam, c1, c2, c3 = oracle.constants(3, m)[:4]
+    lam, a, c1 = oracle.constants(3, m)[:3]
     rng = np.random.default_rng(7 + m)
     K = int(rng.integers(0, 2**63))
-    xs = np.array([oracle.trunc_exp(K, i, lam, c1, c2, c3) for i in range(1, 30001)])
+    xs = np.array([oracle.trunc_exp(K, i, lam, a, c1) for i in range(1, 30001)])
     assert xs.min() >= 0.0 and xs.max() < 1.0
     assert stats.kstest(xs, _te_cdf(lam)).pvalue > 1e-3
+
+
+def _remainder_cdf(lam):
+    """CDF of the density proportional to e^{-lambda x} - e^{-lambda} on [0, 1):
+    what is left of Exp(lambda; 0, 1) once its uniform part (weight
+    lambda/(e^lambda - 1)) is taken away."""
+    tot = (1 - math.exp(-lam)) / lam - math.exp(-lam)
+    return lambda x: ((1 - np.exp(-lam * x)) / lam - x * math.exp(-lam)) / tot
+
+
+@pytest.mark.parametrize("variant,m,i", [(3, 2, 0), (3, 4, 0), (3, 16, 0), (4, 64, 63), (4, 64, 40)])
+def test_truncated_exponential_second_branch_law(oracle, variant, m, i):
+    """The draws that miss the uniform part follow the remainder of the density
+    (the sampler's proposals, tangent and chord tests and expm1 test together),
+    so the mixture is exactly Exp(lambda; 0, 1)."""
+    lam, a, c1 = oracle.constants(variant, m, i)[:3]
+    K = 4242 + m + i
+    xs = []
+    pt = 1
+    while len(xs) < 6000:
+        if c1 * (float(oracle.word(K, pt, 0) >> 32) * 2.0 ** -32) >= 1.0:
+            xs.append(oracle.trunc_exp(K, pt, lam, a, c1))
+        pt += 1
+    assert stats.kstest(np.array(xs), _remainder_cdf(lam)).pvalue > 1e-3
+
+
+def test_truncated_exponential_proposal_cap(oracle):
+    """With one proposal allowed, a rejected proposal is returned as it is: the
+    capped path gives the first proposal's x whatever the tests decide."""
+    m = 2
+    lam, a, c1 = oracle.constants(3, m)[:3]
+    K = 99
+    capped = diff = 0
+    for pt in range(1, 4000):
+        if c1 * (float(oracle.word(K, pt, 0) >> 32) * 2.0 ** -32) < 1.0:
+            continue
+        x1 = float(oracle.word(K, pt, 16) >> 11) * 2.0 ** -53
+        assert oracle.trunc_exp(K, pt, lam, a, c1, rounds=1) == x1
+        capped += 1
+        diff += oracle.trunc_exp(K, pt, lam, a, c1) != x1
+    assert capped > 500 and diff > 100  # the uncapped sampler rejects some first proposals
 
 
 def test_truncated_exponential_law_rate_log2(oracle):
     """The largest rate ProbMinHash4 uses, lambda_{m-1} = log 2 (Sec. 2.8)."""
     m = 64
-    lam, c1, c2, c3 = oracle.constants(4, m, m - 1)[:4]
+    lam, a, c1 = oracle.constants(4, m, m - 1)[:3]
     assert lam == pytest.approx(math.log(2), rel=1e-15)
+    assert a == 1.0
     K = 12345
-    xs = np.array([oracle.trunc_exp(K, i, lam, c1, c2, c3) for i in range(1, 30001)])
+    xs = np.array([oracle.trunc_exp(K, i, lam, a, c1) for i in range(1, 30001)])
     assert stats.kstest(xs, _te_cdf(lam)).pvalue > 1e-3
 
 
@@ -178,10 +258,10 @@ def test_truncated_exponential_fast_path_rate(oracle):
     gold = json.load(open(GOLDEN))
     for m, lam_idx in ((16, None), (256, None), (64, 63)):
         if lam_idx is None:
-            lam, c1 = oracle.constants(3, m)[:2]
+            c1 = oracle.constants(3, m)[2]
             expect = (m - 1) * math.log1p(1.0 / (m - 1))
         else:
-            lam, c1 = oracle.constants(4, m, lam_idx)[:2]
+            c1 = oracle.constants(4, m, lam_idx)[2]
             expect = gold["te_fast_path_worst"]["probability"]
         K = 777 + m
         N = 40000
@@ -197,20 +277,23 @@ def test_constants_closed_forms(oracle):
     import mpmath
     mpmath.mp.prec = 200
     for m in (2, 3, 64, 1024, 4096, 16384):
-        lam, c1, c2, c3 = oracle.constants(3, m)[:4]
+        lam, a, c1 = oracle.constants(3, m)[:3]
         L = mpmath.log(1 + mpmath.mpf(1) / (m - 1))
         assert abs(lam - float(L)) <= 2 * ulp(float(L))
-        for got, ref in ((c1, (mpmath.e ** L - 1) / L), (c2, mpmath.log(2 / (1 + mpmath.e ** -L)) / L),
-                         (c3, (1 - mpmath.e ** -L) / L)):
-            assert abs(got - float(ref)) <= 4 * ulp(float(ref)), (m, got, ref)
+        assert a == 1.0 / (m - 1)  # e^lambda - 1 = 1/(m-1)
+        ref = (mpmath.e ** L - 1) / L
+        assert abs(c1 - float(ref)) <= 4 * ulp(float(ref)), (m, c1, ref)
     for m in (2, 5, 64, 1024):
         row1 = oracle.constants(4, m, 1)
-        assert row1[4] == 1.0  # gamma_1 = log(1+1/(m-1))/lambda_1 = 1 exactly
-        assert row1[6] == pytest.approx(1.0 / row1[0], rel=0)  # delta = 1/lambda_1
+        assert row1[3] == 1.0  # gamma_1 = log(1+1/(m-1))/lambda_1 = 1 exactly
+        assert row1[5] == pytest.approx(1.0 / row1[0], rel=0)  # delta = 1/lambda_1
         prev = 0.0
         for i in range(1, m):
             row = oracle.constants(4, m, i)
-            g = row[4]
+            Li = mpmath.log(1 + mpmath.mpf(1) / (m - i))
+            assert abs(row[0] - float(Li)) <= 2 * ulp(float(Li))
+            assert row[1] == 1.0 / (m - i)
+            g = row[3]
             ref = float(mpmath.log(1 + mpmath.mpf(i) / (m - i)) / mpmath.log(1 + mpmath.mpf(1) / (m - 1)))
             assert abs(g - ref) <= 8 * ulp(ref)
             assert g > prev  # boundaries strictly increase
@@ -261,7 +344,7 @@ def test_stream_monotone_lower_bounds(oracle):
                 lb = winv * np.arange(xs.size)
                 assert (xs >= lb).all()
             if v == 4:
-                g = np.array([0.0] + [oracle.constants(4, m, i)[4] for i in range(1, m)])
+                g = np.array([0.0] + [oracle.constants(4, m, i)[3] for i in range(1, m)])
                 assert (xs >= winv * g).all()
             if v in (2, 4):
                 assert sorted(ls.tolist()) == list(range(m))

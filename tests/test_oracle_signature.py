@@ -1,7 +1,7 @@
 """Pins of the oracle's signature algorithms.
 
-The sequential algorithms (stop limit, tree, Fisher-Yates, lower-bound tests)
-are checked against a brute force that shares none of the stop logic: it
+The sequential algorithms (stop limit, lower-bound tests, the lazily
+initialised permutation) are checked against a brute force that shares none of the stop logic: it
 generates every point of every stream and takes per-label minima (eq. (1) with
 the hash values of eq. (9)).  The interleaved variants of Sec. 2.7 must give
 identical signatures.  Special cases and invariances follow from the
@@ -38,6 +38,42 @@ def test_sequential_equals_brute_force(oracle, variant):
             seq = oracle.sign(variant, seed, m, ids, w)
             brute = oracle.sign(variant, seed, m, ids, w, mode=oracle.MODE_BRUTE)
             assert np.array_equal(seq, brute), (variant, m, n, trial)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_sequential_equals_brute_force_under_forced_caps(oracle, variant):
+    """The capped paths (Sec. 3: bounded loops) -- a short stream cap for
+    ProbMinHash1/3, one proposal for the truncated-exponential sampler, few
+    Lemire redraws with a floor that forces them -- give the same signature
+    whether the stop rule prunes or every point is generated."""
+    rng = np.random.default_rng(150 + variant)
+    ms = [1, 2, 3, 16, 64] if variant <= 2 else [2, 3, 16, 64]
+    hit = 0
+    for caps in (oracle.Caps(imax=3, te_rounds=1, redraws=1, lemire_floor=1 << 31),
+                 oracle.Caps(imax=1, te_rounds=2, redraws=0, lemire_floor=3 << 30),
+                 oracle.Caps(imax=17, te_rounds=1, redraws=8, lemire_floor=(1 << 32) - 1)):
+        for m in ms:
+            for trial in range(25):
+                n = int(rng.integers(1, 9))
+                ids, w = _rand_set(rng, n, ("exp", "wide", "ones")[trial % 3])
+                seed = int(rng.integers(0, 2**63))
+                seq = oracle.sign(variant, seed, m, ids, w, caps=caps)
+                brute = oracle.sign(variant, seed, m, ids, w, mode=oracle.MODE_BRUTE, caps=caps)
+                assert np.array_equal(seq, brute), (variant, m, n, trial)
+                hit += not np.array_equal(seq, oracle.sign(variant, seed, m, ids, w))
+    assert hit > 20  # the caps change results: the capped paths ran
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_stream_cap_truncates(oracle, variant):
+    """A stream cap of I points: the oracle's stream of a single element has
+    exactly I points, and the signature of one element fills at most I
+    components."""
+    caps = oracle.Caps(imax=5)
+    xs, ls = oracle.stream(variant, 64, 12345, 1.0, 100, caps=caps)
+    assert np.count_nonzero(xs) <= 5 and xs[5:].max() == 0.0
+    keys = oracle.sign(variant, SEED, 64, np.array([7], dtype=np.uint64), np.array([1.0]), caps=caps)
+    assert 1 <= int(np.count_nonzero(keys != oracle.EMPTY)) <= 5
 
 
 @pytest.mark.parametrize("variant", [1, 3])

@@ -144,12 +144,29 @@ def test_pmh4_unit_weights_superminhash_variance(oracle):
 
 
 def test_alpha_values(oracle):
+    """alpha(m, u) of eq. (8) against values worked out by hand.
+
+    * m = 4, u = 2: the summand l^2 ((l+1)^2 + (l-1)^2 - 2 l^2) is 2 l^2, so
+      the sum over l = 1..3 is 28 and the denominator 3 * 16 * 1 = 48:
+      alpha = 1 - 28/48 = 5/12.
+    * u = 2 in general: the same summand gives 2 sum l^2 = (m-1) m (2m-1)/3
+      over (m-1) m^2, so alpha(m, 2) = 1 - (2m-1)/(3m) = (m+1)/(3m).
+    * u = 3: (l+1)^3 + (l-1)^3 - 2 l^3 = 6 l, the sum is 6 sum l^4 with
+      sum_{l<m} l^4 = (m-1) m (2m-1) (3m^2 - 3m - 1)/30, so
+      alpha(m, 3) = 1 - (2m-1)(3m^2 - 3m - 1) / (10 (m-1) m^2); m = 2 gives 5/8.
+    * alpha = 1 for u = 1 (one element: J is 0 or 1) and for m = 1.
+    """
+    from fractions import Fraction as F
+    assert oracle.alpha_superminhash(4, 2) == F(5, 12)
+    assert oracle.alpha_superminhash(2, 3) == F(5, 8)
+    for m in (2, 3, 5, 16, 64, 1000):
+        assert oracle.alpha_superminhash(m, 2) == F(m + 1, 3 * m)
+        assert oracle.alpha_superminhash(m, 3) == 1 - F((2 * m - 1) * (3 * m * m - 3 * m - 1), 10 * (m - 1) * m * m)
     assert oracle.alpha_superminhash(4, 1) == 1
-    # independent components when m = 1
     assert oracle.alpha_superminhash(1, 5) == 1
-    for m, u in ((4, 2), (16, 8), (64, 10)):
-        a = float(oracle.alpha_superminhash(m, u))
-        assert 0.3 < a < 0.7
+    # below the union size the factor stays near one half (text after eq. (8))
+    for m, u in ((16, 8), (64, 10), (1024, 100)):
+        assert 0.4 < float(oracle.alpha_superminhash(m, u)) < 0.6
 
 
 @pytest.mark.parametrize("variant,rate", [(1, "1/m"), (2, "1/m"), (3, "pmh3"), (4, "pmh3")])
