@@ -91,8 +91,10 @@ typedef struct {
 
 /* Create a context for (seed, m, variant) on the current device.  variant is
  * 1..4 for ProbMinHash1..4.  Builds the per-m constant tables on the device
- * (beta_i of Sec. 2.4; lambda, sampler constants c1..c3 of Sec. 2.8; lambda_i,
- * gamma_i, delta of Sec. 2.6).  Synchronous.  *out receives the context. */
+ * (beta_i of Sec. 2.4; lambda, a = e^lambda - 1 and c1 = a/lambda of the
+ * truncated-exponential sampler of Sec. 2.8; lambda_i, a_i, c1_i, gamma_i,
+ * delta of Sec. 2.6) and sets the default loop caps (see pmh_set_caps).
+ * Synchronous.  *out receives the context. */
 int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out);
 
 /* Free the context and its device memory (synchronizes the device). */
@@ -104,9 +106,14 @@ uint32_t pmh_max_m(int variant);
 /* Human-readable text for a status code (static storage). */
 const char* pmh_status_str(int status);
 
-/* Signatures of num_sets weighted sets in one persistent launch (plus one
- * ordering kernel): sets are taken heavy-first from a device work list.
- * ids, weights, offsets [device]; outputs [device] or NULL. */
+/* ProbMinHash signatures (eq. (1): component k holds the element whose
+ * point labelled k has the smallest value; the points are the per-element
+ * streams of Sec. 2.1 with the variant's value and label laws of Sec. 2.3
+ * (ProbMinHash1), 2.4 (ProbMinHash2), 2.5 (ProbMinHash3) or 2.6
+ * (ProbMinHash4); the stop rule of Sec. 2 only prunes) of num_sets weighted
+ * sets in one persistent launch (plus one ordering kernel): sets are taken
+ * heavy-first from a device work list.  ids, weights, offsets [device];
+ * outputs [device] or NULL. */
 int pmh_hash_sets(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
                   uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
                   uint64_t* out_keys, void* stream);
@@ -188,6 +195,24 @@ int pmh_get_status(pmh_ctx* ctx, void* stream);
 int pmh_set_tuning(pmh_ctx* ctx, const pmh_tuning* t);
 int pmh_get_tuning(const pmh_ctx* ctx, pmh_tuning* t);
 
+/* Loop caps of the random streams (Sec. 3 advises bounding every loop of the
+ * generators).  Unlike the tuning they are part of the result's definition,
+ * and the CPU reference takes the same four values:
+ *   imax          points per element of the with-replacement streams
+ *                 (ProbMinHash1/3; 0: the default 6 m bitlen(m) + 64, at most
+ *                 2^24 - 1), the stream ends after point imax;
+ *   te_rounds     proposals of the truncated-exponential sampler's second
+ *                 branch (Sec. 2.8; 1..32, default 32), the last proposal is
+ *                 returned when all are rejected;
+ *   redraws       redraws of Lemire's bounded integers (0..8, default 8);
+ *   lemire_floor  validation only: draws whose low product half lies below it
+ *                 are redrawn as well, which forces the redraw path (labels
+ *                 are then no longer uniform); 0 in normal use.
+ * Applies to later calls of every hashing entry point of the context
+ * (P-MinHash has no such loops).  Returns PMH_ERR_ARG for values out of
+ * range. */
+int pmh_set_caps(pmh_ctx* ctx, uint32_t imax, uint32_t te_rounds, uint32_t redraws, uint32_t lemire_floor);
+
 /* Time candidate schedules on the given batch ([device] inputs, the batch is
  * hashed trials times per candidate) and keep the fastest in the context;
  * *best (host, may be NULL) receives it.  Synchronous. */
@@ -201,14 +226,17 @@ int pmh_estimate(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB,
                  uint32_t m, double* out);
 
 /* Equal-component counts for `pairs` signature pairs, [device] inputs laid out
- * [pairs][m]; counts[pairs] uint32 [device].  Divide by m for eq. (3). */
+ * [pairs][m] (pair r compares row r of A with row r of B; empty components,
+ * idx 0xFFFFFFFF, never count); counts[pairs] uint32 [device].  Divide by m
+ * for eq. (3).  pairs <= 2^31 - 1. */
 int pmh_estimate_pairs(const uint64_t* idA, const uint32_t* idxA, const uint64_t* idB,
                        const uint32_t* idxB, uint32_t m, uint64_t pairs, uint32_t* counts,
                        void* stream);
 
-/* All-pairs equal-component counts over k signatures of m 32-bit
- * fingerprints fp[k][m] [device] (0 = empty component, never equal);
- * counts[k][k] uint16 [device], saturating at 65535. */
+/* The numerators of eq. (3) for all pairs of k signatures: equal-component
+ * counts over k signatures of m 32-bit fingerprints fp[k][m] [device] (0 =
+ * empty component, never equal); counts[k][k] uint16 [device], saturating at
+ * 65535. */
 int pmh_allpairs_counts(const uint32_t* fp, uint32_t k, uint32_t m, uint16_t* counts, void* stream);
 
 /* b-bit reduction (Sec. 1.3, algorithm "Reduction to a b-bit signature") of
@@ -226,9 +254,10 @@ int pmh_bbit_pack(const uint64_t* id, uint64_t num_sigs, uint32_t m, uint32_t b,
 int pmh_bbit_allpairs(const uint64_t* sig, uint32_t k, uint32_t m, uint32_t b, uint16_t* counts, void* stream);
 
 /* Copy a constant table to [host] out (count doubles).  which: 0 beta (PMH2,
- * m+1), 1 lambda_i, 2 c1_i, 3 c2_i, 4 c3_i, 5 gamma_i, 6 dgamma_i (PMH4, m
- * each), 7 scalars {lambda, c1, c2, c3, delta, 0, 0, 0} (8), 8 expm1
- * coefficients (19), 9 stream-logarithm cells (512: 256 pairs (1/c_j, L_j)).
+ * m+1), 1 lambda_i, 2 a_i = e^lambda_i - 1, 3 c1_i = a_i/lambda_i,
+ * 5 gamma_i, 6 dgamma_i (PMH4, m each), 7 scalars {lambda, a, c1 (PMH3), 0,
+ * delta (PMH4), 0, 0, 0} (8), 8 expm1 coefficients (19), 9 stream-logarithm
+ * cells (512: 256 pairs (1/c_j, L_j)); 4 is not used (PMH_ERR_ARG).
  * Synchronous. */
 int pmh_get_table(pmh_ctx* ctx, int which, double* out, uint32_t count);
 

@@ -21,15 +21,25 @@ constexpr uint32_t kStatusSetTooLarge = 2u; // a set above 2^20 elements was lef
 struct Tables {
   double* beta;   // PMH2: [m+1], beta[i] = m/(m-i+1)
   double* lam;    // PMH4: [m], lambda_i = log(1 + 1/(m-i)), i = 1..m-1
-  double* c1;     // PMH4: [m] sampler constants per i
-  double* c2;
-  double* c3;
+  double* a;      // PMH4: [m], a_i = e^lambda_i - 1 = 1/(m-i)
+  double* c1;     // PMH4: [m], c1_i = a_i / lambda_i
   double* gam;    // PMH4: [m], gamma_0 = 0, gamma_i = log(1 + i/(m-i))/lambda_1
   double* dgam;   // PMH4: [m], gamma_i - gamma_{i-1}
   double* expm1c; // [19] Taylor coefficients 1/k! built by repeated division
-  double* scal;   // [8]: lambda, c1, c2, c3 (PMH3), delta (PMH4)
+  double* scal;   // [8]: lambda, a, c1 (PMH3), -, delta (PMH4)
   double* ltab;   // [512]: stream-logarithm cells (inv_j, -log inv_j), then (inv_j, -log 2 inv_j)
+  // Loop caps (Sec. 3 advises bounding the generators' loops; part of the
+  // result's definition): proposals of the truncated-exponential sampler
+  // (1..32), Lemire redraws (0..8) and a validation-only floor that forces
+  // redraws of draws whose low product half lies below it (0: off).
+  uint32_t te_rounds;
+  uint32_t redraws;
+  uint32_t lemire_floor;
 };
+constexpr uint32_t kTeRoundsMax = 32;  // word slots 16..79
+constexpr uint32_t kRedrawsMax = 8;    // word slots 1..8
+// Largest stream cap: word counters address point i as i << 8 in 32 bits.
+constexpr uint32_t kImaxMax = (1u << 24) - 1;
 
 // Tunables of the per-set algorithm (chosen by the autotuner or defaults).
 struct Tuning {

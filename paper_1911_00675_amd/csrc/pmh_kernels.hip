@@ -205,50 +205,62 @@ __device__ __forceinline__ double exp1(uint64_t w, const LogCell* tab) {
   return 0.0 - stream_log<kAsm>(upos32(w), tab);
 }
 
-// Rejection part of the truncated-exponential sampler (Sec. 2.8).
-__device__ __attribute__((noinline)) double te_slow(uint64_t pb, double lam, double c1, double c2,
-                                                    double c3, const double* em) {
+// Truncated exponential Exp(lam; 0, 1) of Sec. 2.8, density
+// f(x) = lam e^(-lam x) / (1 - e^(-lam)) on [0, 1), with a = e^lam - 1 and
+// c1 = a / lam.  f never falls below 1/c1 (its value at x -> 1), so f is a
+// mixture: the uniform law with weight 1/c1, and a remainder proportional to
+// e^(-lam x) - e^(-lam) = e^(-lam) expm1(lam (1 - x)).
+//   Fast path: x = c1 U from the high half of the point's word 0 is below 1
+//   with probability 1/c1 and then uniform.
+//   Otherwise (te_slow): the remainder by proposals (x, v) uniform on
+//   [0,1)^2 from the 53-bit slot pairs (16 + 2r, 17 + 2r), accepted when
+//   v a <= expm1(lam t), t = 1 - x.  expm1(lam t) lies between lam t (its
+//   tangent at 0) and a t (its chord on [0, 1]), so v c1 <= t accepts and
+//   v >= t rejects without the series; at most `rounds` proposals, the last
+//   one's x is returned.
+__device__ __attribute__((noinline)) double te_slow(uint64_t pb, double lam, double a, double c1, uint32_t rounds,
+                                                    const double* em) {
   double x = 0.0;
-  for (uint32_t it = 0; it < 32; ++it) {
-    x = u53(word(pb, 16u + 2u * it));
-    if (x < c2) return x;
-    double y = 0.5 * u53(word(pb, 17u + 2u * it));
-    if (y > 1.0 - x) {
-      x = 1.0 - x;
-      y = 1.0 - y;
-    }
-    if (x <= c3 * (1.0 - y)) return x;
-    double yc = y * c1;
-    if (yc <= 1.0 - x) return x;
-    if (yc * lam <= spec_expm1(lam * (1.0 - x), em)) return x;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    x = u53(word(pb, 16u + 2u * r));
+    const double v = u53(word(pb, 17u + 2u * r));
+    const double t = 1.0 - x;  // exact: x is a multiple of 2^-53 in [0, 1)
+    if (v * c1 <= t) return x;
+    if (v < t && v * a <= spec_expm1(lam * t, em)) return x;
   }
   return x;
 }
-// Exp(lam; 0, 1): the rectangle below e^-lam first (taken with probability
-// lam/(e^lam - 1)), rejection otherwise.  w0 = the point's word 0.
-__device__ __forceinline__ double trunc_exp(uint64_t w0, uint64_t pb, double lam, double c1, double c2, double c3,
-                                            const double* em) {
-  double x = c1 * u32v(w0);
+// w0 = the point's word 0, pb its counter base.
+__device__ __forceinline__ double trunc_exp(uint64_t w0, uint64_t pb, double lam, double a, double c1,
+                                            const Tables& t) {
+  const double x = c1 * u32v(w0);
   if (x < 1.0) return x;
-  return te_slow(pb, lam, c1, c2, c3, em);
+  return te_slow(pb, lam, a, c1, t.te_rounds, t.expm1c);
 }
 
-__device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_t s, uint64_t prod) {
+// Redraws of Lemire's method: a draw whose low product half lies below
+// (2^32 - s) mod s (or below the validation floor) is biased and takes the
+// low half of the next word of slots 1..redraws.
+__device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_t s, uint64_t prod,
+                                                           uint32_t redraws, uint32_t floor) {
   uint32_t thr = (0u - s) % s;
+  thr = thr < floor ? floor : thr;
   uint32_t lo = (uint32_t)prod;
-  for (uint32_t r = 1; lo < thr && r <= 8; ++r) {
-    uint64_t x = word(pb, r) & 0xFFFFFFFFull;
+  for (uint32_t r = 1; lo < thr && r <= redraws; ++r) {
+    const uint64_t x = word(pb, r) & 0xFFFFFFFFull;
     prod = x * (uint64_t)s;
     lo = (uint32_t)prod;
   }
   return prod;
 }
 // Uniform integer in [0, s) (Lemire's multiply-shift with rejection) from the
-// low half of the point's word 0; redraws from words 1..8.
-__device__ __forceinline__ uint32_t lemire(uint64_t w0, uint64_t pb, uint32_t s) {
-  uint64_t x = w0 & 0xFFFFFFFFull;
+// low half of the point's word 0.  The threshold is below s (and below the
+// floor), so a low half of at least max(s, floor) needs no redraw.
+__device__ __forceinline__ uint32_t lemire(uint64_t w0, uint64_t pb, uint32_t s, const Tables& t) {
+  const uint64_t x = w0 & 0xFFFFFFFFull;
   uint64_t prod = x * (uint64_t)s;
-  if ((uint32_t)prod < s) prod = lemire_redraw(pb, s, prod);
+  const uint32_t lim = s > t.lemire_floor ? s : t.lemire_floor;
+  if ((uint32_t)prod < lim) prod = lemire_redraw(pb, s, prod, t.redraws, t.lemire_floor);
   return (uint32_t)(prod >> 32);
 }
 
@@ -462,13 +474,13 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       if (key >= kmax) return step + 1;
       if (x >= R.Tprev) {
         PMH_STAT(sm, kStLaneApply, 1);
-        lds_min(keys, lemire(w0, pb, m), key);
+        lds_min(keys, lemire(w0, pb, m, t), key);
       }
       if (i == R.imax) return step + 1;
       ++i;
     }
   } else if constexpr (V == 3) {
-    const double lam = t.scal[0], c1 = t.scal[1], c2 = t.scal[2], c3 = t.scal[3];
+    const double lam = t.scal[0], a3 = t.scal[1], c13 = t.scal[2];
     uint32_t i = i0;
     uint64_t pb = pbase(K, i0);
     for (int step = 0;; ++step, pb += kPointStep) {
@@ -480,12 +492,12 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         return step;
       }
       const uint64_t w0 = mix64(pb);
-      const double x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, lam, c1, c2, c3, t.expm1c);
+      const double x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, lam, a3, c13, t);
       const uint64_t key = make_key(x, p);
       PMH_STAT(sm, kStLanePts, 1);
       if (x >= R.Tprev && key < kmax) {
         PMH_STAT(sm, kStLaneApply, 1);
-        lds_min(keys, lemire(w0, pb, m), key);
+        lds_min(keys, lemire(w0, pb, m, t), key);
       }
       if (i == R.imax) return step + 1;
       ++i;
@@ -516,12 +528,12 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         if (A.binary)
           x = lb + u32v(w0);
         else if (i < m)
-          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
+          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.a[i], t.c1[i], t));
         else
           x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
       }
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
-      const uint32_t j = (i - 1) + lemire(w0, pb, m - i + 1);
+      const uint32_t j = (i - 1) + lemire(w0, pb, m - i + 1, t);
       uint32_t l = j, v = i - 1;
 #pragma unroll
       for (uint32_t s = 0; s < step; ++s) {
@@ -596,7 +608,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t);
         key = make_key(x, p);
       }
     } else {
@@ -609,7 +621,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
         if (A.binary)
           x = (double)(i - 1) + u32v(w0);
         else if (i < m)
-          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.c1[i], t.c2[i], t.c3[i], t.expm1c));
+          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.a[i], t.c1[i], t));
         else
           x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
         key = make_key(x, p);
@@ -625,7 +637,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
     }
     uint32_t label = 0;
     if constexpr (V == 1 || V == 3) {
-      if (apply) label = lemire(w0, pb, m);
+      if (apply) label = lemire(w0, pb, m, t);
     } else {
       // 64 Fisher-Yates steps at once.  Step L (point i0+L) consumes position
       // P = i-1 and draws slot j >= P; its label is g[j] as the latest earlier
@@ -638,7 +650,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       // those latest steps; chains of steps writing each other's positions
       // are resolved by pointer jumping.
       const int P = (int)i - 1;
-      const int j = active ? P + (int)lemire(w0, pb, m - i + 1) : -1;
+      const int j = active ? P + (int)lemire(w0, pb, m - i + 1, t) : -1;
       const int r = j - ((int)i0 - 1);  // window index of slot j (>= lane)
       const int h = j & (kFyBuckets - 1);
       const bool inwin = active && j != P && r < 64;
@@ -766,7 +778,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t);
         key = make_key(x, p);
       }
     }
@@ -778,7 +790,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
     if (have && j == 0) PMH_STAT(sm, kStMiniPts, first);
     if (apply) {
       PMH_STAT(sm, kStApply, 1);
-      lds_min(keys, lemire(w0, pb, m), key);
+      lds_min(keys, lemire(w0, pb, m, t), key);
     }
     const uint64_t tlast = shfl_u64(tl, leader + G - 1);
     if (have) {
@@ -1492,28 +1504,26 @@ __global__ void k_init_tables(int variant, uint32_t m, Tables t) {
     t.ltab[2 * (128 + i) + 1] = 0.0 - spec_log(2.0 * inv);
   }
   if (variant == 2 && i <= m) t.beta[i] = i == 0 ? 0.0 : (double)m / (double)(m - i + 1);
-  if (variant == 3 && i == 0) {
+  if (variant == 3 && i == 0) {  // lambda = log(1 + 1/(m-1)), so e^lambda - 1 = 1/(m-1) exactly
     const double a = 1.0 / (double)(m - 1);
     const double lam = spec_log1p(a);
     t.scal[0] = lam;
-    t.scal[1] = a / lam;
-    t.scal[2] = spec_log1p(1.0 / (double)(2 * m - 1)) / lam;
-    t.scal[3] = (1.0 / (double)m) / lam;
+    t.scal[1] = a;
+    t.scal[2] = a / lam;
   }
   if (variant == 4 && i < m) {
     const double lam1 = spec_log1p(1.0 / (double)(m - 1));
     if (i == 0) {
-      t.lam[0] = t.c1[0] = t.c2[0] = t.c3[0] = 0.0;
+      t.lam[0] = t.a[0] = t.c1[0] = 0.0;
       t.gam[0] = 0.0;
       t.dgam[0] = 0.0;
       t.scal[4] = 1.0 / lam1;
     } else {
       const double a = 1.0 / (double)(m - i);
       const double l = spec_log1p(a);
-      t.lam[i] = l;
+      t.lam[i] = l;  // e^lambda_i - 1 = 1/(m-i) exactly
+      t.a[i] = a;
       t.c1[i] = a / l;
-      t.c2[i] = spec_log1p(1.0 / (double)(2 * (m - i) + 1)) / l;
-      t.c3[i] = (1.0 / (double)(m - i + 1)) / l;
       const double gi = spec_log1p((double)i / (double)(m - i)) / lam1;
       const double gp = i == 1 ? 0.0 : spec_log1p((double)(i - 1) / (double)(m - i + 1)) / lam1;
       t.gam[i] = gi;
@@ -1677,12 +1687,12 @@ __global__ void k_debug(int what, const double* in, const uint64_t* in_u, double
     case 4: out_u[k] = mix64(in_u[k]); break;
     case 5: {
       const uint64_t pb = pbase(in_u[k], (uint32_t)k + 1);
-      out[k] = trunc_exp(mix64(pb), pb, t.scal[0], t.scal[1], t.scal[2], t.scal[3], t.expm1c);
+      out[k] = trunc_exp(mix64(pb), pb, t.scal[0], t.scal[1], t.scal[2], t);
       break;
     }
     case 6: {
       const uint64_t pb = pbase(in_u[k], (uint32_t)k + 1);
-      out_u[k] = lemire(mix64(pb), pb, m);
+      out_u[k] = lemire(mix64(pb), pb, m, t);
       break;
     }
     case 7: out_u[k] = spacing_fixed(exp1(mix64(pbase(in_u[k], (uint32_t)k + 1)), (const LogCell*)t.ltab)); break;

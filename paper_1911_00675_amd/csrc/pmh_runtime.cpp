@@ -120,7 +120,7 @@ HashArgs make_args(const pmh_ctx* c, const uint64_t* ids, const double* w, const
   a.out_keys = keys;
   a.seedhash = c->seedhash;
   a.m = c->m;
-  a.imax = imax_for(c->m);
+  a.imax = c->imax;
   a.t = c->t;
   a.c0 = c->tune.c0;
   a.grow = c->tune.grow;
@@ -240,8 +240,8 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   }
   c->num_cu = prop.multiProcessorCount;
   plan_queues(c);
-  // constant tables: 7 arrays of m+1 doubles + expm1 (19) + scalars (8) + log cells (512)
-  const size_t nd = 7 * (size_t)(m + 1) + 19 + 8 + 512;
+  // constant tables: 6 arrays of m+1 doubles + expm1 (19) + scalars (8) + log cells (512)
+  const size_t nd = 6 * (size_t)(m + 1) + 19 + 8 + 512;
   if (hipMalloc(&c->table_mem, nd * sizeof(double)) != hipSuccess) {
     delete c;
     return PMH_ERR_OOM;
@@ -249,14 +249,17 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   double* d = (double*)c->table_mem;
   c->t.beta = d;
   c->t.lam = d + 1 * (size_t)(m + 1);
-  c->t.c1 = d + 2 * (size_t)(m + 1);
-  c->t.c2 = d + 3 * (size_t)(m + 1);
-  c->t.c3 = d + 4 * (size_t)(m + 1);
-  c->t.gam = d + 5 * (size_t)(m + 1);
-  c->t.dgam = d + 6 * (size_t)(m + 1);
-  c->t.expm1c = d + 7 * (size_t)(m + 1);
+  c->t.a = d + 2 * (size_t)(m + 1);
+  c->t.c1 = d + 3 * (size_t)(m + 1);
+  c->t.gam = d + 4 * (size_t)(m + 1);
+  c->t.dgam = d + 5 * (size_t)(m + 1);
+  c->t.expm1c = d + 6 * (size_t)(m + 1);
   c->t.scal = c->t.expm1c + 19;
   c->t.ltab = c->t.scal + 8;
+  c->imax = imax_for(m);
+  c->t.te_rounds = kTeRoundsMax;
+  c->t.redraws = kRedrawsMax;
+  c->t.lemire_floor = 0;
   int rc = PMH_OK;
   if (hipMemset(c->table_mem, 0, nd * sizeof(double)) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipMalloc(&c->status, sizeof(uint32_t)) != hipSuccess) rc = PMH_ERR_OOM;
@@ -284,6 +287,7 @@ void pmh_destroy(pmh_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   free_work(&c->work);
+  free_work(&c->gwork);
   for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->table_mem) (void)hipFree(c->table_mem);
   if (c->status) (void)hipFree(c->status);
@@ -450,11 +454,13 @@ int pmh_hash_sets_graph(pmh_ctx* c, const uint64_t* ids, const double* w, const 
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->gexec = nullptr;
     c->graph = nullptr;
-    rc = ensure_work(c, &c->work, num_sets);
+    // The graph keeps the device addresses of its work buffer: it owns one
+    // that no other call reallocates (the shared one grows with later calls).
+    rc = ensure_work(c, &c->gwork, num_sets);
     if (rc) return rc;
-    HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
+    HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->gwork);
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PMH_ERR_DEVICE;
-    rc = enqueue_batched(c, a, &c->work, c->cap_stream);
+    rc = enqueue_batched(c, a, &c->gwork, c->cap_stream);
     hipGraph_t gr = nullptr;
     const hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
     if (rc) {
@@ -504,6 +510,18 @@ int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
   c->tune.split_log2 = t->split_log2;
   c->tune.c0_split = t->c0_split;
   c->tune_version++;
+  return PMH_OK;
+}
+
+int pmh_set_caps(pmh_ctx* c, uint32_t imax, uint32_t te_rounds, uint32_t redraws, uint32_t lemire_floor) {
+  if (!c || imax > kImaxMax || te_rounds < 1 || te_rounds > kTeRoundsMax || redraws > kRedrawsMax)
+    return PMH_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->imax = imax ? imax : imax_for(c->m);
+  c->t.te_rounds = te_rounds;
+  c->t.redraws = redraws;
+  c->t.lemire_floor = lemire_floor;
+  c->tune_version++;  // a cached graph holds the previous caps
   return PMH_OK;
 }
 
@@ -570,9 +588,8 @@ int pmh_get_table(pmh_ctx* c, int which, double* out, uint32_t count) {
   switch (which) {
     case 0: src = c->t.beta; avail = c->m + 1; break;
     case 1: src = c->t.lam; avail = c->m; break;
-    case 2: src = c->t.c1; avail = c->m; break;
-    case 3: src = c->t.c2; avail = c->m; break;
-    case 4: src = c->t.c3; avail = c->m; break;
+    case 2: src = c->t.a; avail = c->m; break;
+    case 3: src = c->t.c1; avail = c->m; break;
     case 5: src = c->t.gam; avail = c->m; break;
     case 6: src = c->t.dgam; avail = c->m; break;
     case 7: src = c->t.scal; avail = 8; break;

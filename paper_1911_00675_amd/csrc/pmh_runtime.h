@@ -67,6 +67,8 @@ struct pmh_ctx {
   uint32_t* status = nullptr;
   uint64_t* stats = nullptr;  // event counters of the statistics build
   pmh::WorkBuf work;
+  pmh::WorkBuf gwork;  // the cached graph's own work buffer
+  uint32_t imax = 0;   // ProbMinHash1/3 stream cap
   pmh::Tuning tune;
   uint64_t tune_version = 0;
   hipStream_t cap_stream = nullptr;

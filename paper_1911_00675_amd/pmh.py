@@ -43,6 +43,7 @@ SIGNATURES = {
     "pmh_timing_begin": (_i32, [_vp, _i32]),
     "pmh_timing_read": (_i32, [_vp, _vp, _i32]),
     "pmh_set_tuning": (_i32, [_vp, _vp]),
+    "pmh_set_caps": (_i32, [_vp, _u32, _u32, _u32, _u32]),
     "pmh_get_tuning": (_i32, [_vp, _vp]),
     "pmh_autotune": (_i32, [_vp] * 4 + [_u64, _i32, _vp, _vp]),
     "pmh_estimate": (_i32, [_vp, _vp, _vp, _vp, _u32, _vp]),
@@ -121,6 +122,34 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _check_batch(ids, weights, offsets, out, m):
+    """Host-side shape checks the C ABI cannot make: the element arrays cover
+    offsets[-1] entries and every output holds num_sets x m entries."""
+    num_sets = int(offsets.numel()) - 1
+    if num_sets < 0 or offsets.dim() != 1:
+        raise ValueError("offsets must be a 1-D tensor of num_sets + 1 entries")
+    n = 0
+    if num_sets > 0:
+        # offsets[-1] costs a device sync; it is remembered on the tensor until
+        # the tensor is modified in place (its version counter moves)
+        memo = getattr(offsets, "_pmh_total", None)
+        if memo is not None and memo[0] == offsets._version:
+            n = memo[1]
+        else:
+            n = int(offsets[-1].item())
+            offsets._pmh_total = (offsets._version, n)
+    if ids.numel() < n:
+        raise ValueError(f"ids holds {ids.numel()} entries, offsets[-1] = {n}")
+    if weights is not None and weights.numel() < n:
+        raise ValueError(f"weights holds {weights.numel()} entries, offsets[-1] = {n}")
+    if out is not None:
+        for name in ("idx", "val", "id", "keys"):
+            t = getattr(out, name)
+            if t is not None and t.numel() != num_sets * m:
+                raise ValueError(f"out.{name} holds {t.numel()} entries, expected {num_sets} x {m}")
+    return num_sets
+
+
 def to_device(arr: np.ndarray, device="cuda"):
     """numpy -> device tensor, uint64 carried as int64 bits."""
     torch = _torch()
@@ -184,7 +213,7 @@ class Context:
         "binary" (the unit-weight specialisation of the context's variant;
         weights must be None)."""
         torch = _torch()
-        num_sets = int(offsets.numel()) - 1
+        num_sets = _check_batch(ids, weights, offsets, out, self.m)
         if out is None:
             out = self.alloc_outputs(num_sets, outputs)
         i64 = (torch.int64, torch.uint64)
@@ -219,9 +248,11 @@ class Context:
         """Add a CSR batch of new elements (weights None: binary weights) to the
         sets of state, in place; out may receive positions and values."""
         torch = _torch()
-        num_sets = int(offsets.numel()) - 1
+        num_sets = _check_batch(ids, weights, offsets, out, self.m)
         if state.keys.shape != (num_sets, self.m) or state.counts.numel() != num_sets:
             raise ValueError("state does not match the batch's sets or the context's m")
+        if state.id is not None and state.id.numel() != num_sets * self.m:
+            raise ValueError("state.id does not hold num_sets x m entries")
         i64 = (torch.int64, torch.uint64)
         rc = lib().pmh_update_sets(
             self._c, _dptr(ids, i64, "ids"),
@@ -258,6 +289,11 @@ class Context:
         for k, v in kw.items():
             setattr(t, k, v)
         _check(lib().pmh_set_tuning(self._c, ctypes.byref(t)), "pmh_set_tuning")
+
+    def set_caps(self, imax: int = 0, te_rounds: int = 32, redraws: int = 8, lemire_floor: int = 0):
+        """Loop caps of the streams (see pmh_set_caps); they change results."""
+        _check(lib().pmh_set_caps(self._c, int(imax), int(te_rounds), int(redraws), int(lemire_floor)),
+               "pmh_set_caps")
 
     def autotune(self, ids, weights, offsets, trials: int = 3, stream=None) -> dict:
         torch = _torch()

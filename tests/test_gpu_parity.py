@@ -63,11 +63,12 @@ def test_primitives_bitwise(pmh):
     assert np.array_equal(ctx.debug_eval(3, words).view(np.uint64),
                           np.array([O.exp1_of_word(int(wd)) for wd in words]).view(np.uint64))
     assert np.array_equal(ctx.debug_eval(4, words), np.array([O.mix64(int(wd)) for wd in words], dtype=np.uint64))
-    lam, c1, c2, c3 = O.constants(3, m)[:4]
+    lam, a, c1 = O.constants(3, m)[:3]
     Ks = rng.integers(0, 2**63, size=20000, dtype=np.uint64)
     te = ctx.debug_eval(5, Ks)
-    want = np.array([O.trunc_exp(int(K), k + 1, lam, c1, c2, c3) for k, K in enumerate(Ks)])
+    want = np.array([O.trunc_exp(int(K), k + 1, lam, a, c1) for k, K in enumerate(Ks)])
     assert np.array_equal(te.view(np.uint64), want.view(np.uint64))
+    assert (want >= 1.0 / c1).sum() > 10  # the second branch of the sampler is exercised
     lab = ctx.debug_eval(6, Ks)
     assert np.array_equal(lab, np.array([O.lemire(int(K), k + 1, m) for k, K in enumerate(Ks)], dtype=np.uint64))
     xs = np.concatenate([u, np.exp(rng.uniform(-700, 700, 5000))])
@@ -100,15 +101,15 @@ def test_constant_tables_bitwise(pmh, m):
     c2.close()
     c3 = pmh.Context(SEED, m, 3)
     sc = c3.table(7, 8)
-    assert np.array_equal(sc[:4].view(np.uint64), O.constants(3, m)[:4].view(np.uint64))
+    assert np.array_equal(sc[:3].view(np.uint64), O.constants(3, m)[:3].view(np.uint64))
     c3.close()
     c4 = pmh.Context(SEED, m, 4)
-    lam, c1, cc2, c3_, gam, dgam = (c4.table(w, m) for w in (1, 2, 3, 4, 5, 6))
+    lam, a, c1, gam, dgam = (c4.table(w, m) for w in (1, 2, 3, 5, 6))
     delta = c4.table(7, 8)[4]
     for i in range(1, m):
         ref = O.constants(4, m, i)
-        got = np.array([lam[i], c1[i], cc2[i], c3_[i], gam[i], dgam[i], delta])
-        assert np.array_equal(got.view(np.uint64), ref[:7].view(np.uint64)), i
+        got = np.array([lam[i], a[i], c1[i], gam[i], dgam[i], delta])
+        assert np.array_equal(got.view(np.uint64), ref[:6].view(np.uint64)), i
     c4.close()
 
 
@@ -356,3 +357,58 @@ def test_alone_and_in_a_mix(pmh):
         mixed = _host(_keys(ctx, b.subset(order))[0])[0]
         assert np.array_equal(mixed[np.where(order == s)[0][0]], full[s])
     ctx.close()
+
+
+def test_graph_survives_work_buffer_growth(pmh):
+    """A cached graph keeps its own work buffer: a graph call, then a batched
+    call on more sets (which grows the context's shared work buffer), then the
+    same graph call again gives the batched result."""
+    print("graph after work-buffer growth", flush=True)
+    m = 64
+    small = W.random_sets(301, 40, 0, 300, "exp")
+    big = W.random_sets(302, 3000, 0, 40, "exp")
+    ctx = pmh.Context(SEED, m, 1)
+    args = [_dev(small.ids), _dev(small.weights), _dev(small.offsets)]
+    out = ctx.alloc_outputs(small.num_sets)
+    ctx.hash_sets(*args, out=out, mode="graph")
+    first = _host(out)[0].copy()
+    ctx.hash_sets(_dev(big.ids), _dev(big.weights), _dev(big.offsets))
+    out.keys.fill_(0)
+    ctx.hash_sets(*args, out=out, mode="graph")
+    assert ctx.status() == pmh.PMH_OK
+    want = ctx.hash_sets(*args)
+    assert np.array_equal(_host(out)[0], _host(want)[0])
+    assert np.array_equal(first, _host(want)[0])
+    ctx.close()
+
+
+def test_estimate_pairs_device(pmh):
+    """pmh_estimate_pairs (eq. (3) numerators on the device) against the
+    oracle's estimator, pair by pair, with empty sets (all-empty components)
+    and identical pairs among them."""
+    print("estimate_pairs", flush=True)
+    import torch
+    for m in (1, 64, 1000):
+        b = W.random_sets(310 + m, 120, 0, 400, "pareto")
+        pos = [5, 17, 40, 41]  # repeated offsets: empty sets
+        b = W.Batch(b.ids, b.weights, np.insert(b.offsets, pos, b.offsets[pos]))
+        assert (b.sizes() == 0).sum() >= 4
+        ctx = pmh.Context(SEED, m, 1)
+        sig = ctx.hash_sets(_dev(b.ids), _dev(b.weights), _dev(b.offsets))
+        keys, idx, val, ids = _host(sig)
+        rng = np.random.default_rng(m)
+        A = rng.integers(0, b.num_sets, size=500)
+        B = rng.integers(0, b.num_sets, size=500)
+        A[20:30] = pos[0] + np.arange(10) % 2  # empty against non-empty and empty
+        B[:20] = A[:20]  # identical pairs
+        ia, ib = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        counts = pmh.estimate_pairs(sig.id[ia].contiguous(), sig.idx[ia].contiguous(),
+                                    sig.id[ib].contiguous(), sig.idx[ib].contiguous()).cpu().numpy()
+        want = np.array([round(O.estimate(ids[a], idx[a], ids[c], idx[c]) * m) for a, c in zip(A, B)])
+        assert np.array_equal(counts, want), m
+        sizes = b.sizes()
+        for r in range(20):
+            assert counts[r] == (m if sizes[A[r]] > 0 else 0)
+        empty = sizes[A] == 0
+        assert (counts[empty] == 0).all()
+        ctx.close()
