@@ -69,7 +69,8 @@ enum {
   PMH_ERR_DEVICE = 6,         /* HIP runtime error */
   PMH_ERR_OOM = 7,            /* device or host allocation failed */
   PMH_ERR_BUSY = 8,           /* serving queue full */
-  PMH_ERR_NOT_READY = 9       /* serving request still in flight */
+  PMH_ERR_NOT_READY = 9,      /* serving request still in flight */
+  PMH_ERR_SCRATCH_LIMIT = 10  /* pmh_hash_sets_noalloc: more sets than its static work buffer holds */
 };
 
 /* Tunables of the per-set schedule.  None of them changes any result. */
@@ -117,6 +118,21 @@ const char* pmh_status_str(int status);
 int pmh_hash_sets(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
                   uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
                   uint64_t* out_keys, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result
+ * as pmh_hash_sets, with its work list, counters and split-set state taken
+ * from a static device array of the library (one per GPU, 16 MiB, held until
+ * the process ends) instead of context buffers that grow on demand.  The
+ * call itself allocates nothing; inputs and outputs are the caller's as for
+ * pmh_hash_sets.  At most 2^20 sets per call (PMH_ERR_SCRATCH_LIMIT, nothing
+ * enqueued).  Every call of this entry point on one GPU, from any context,
+ * uses the same array, and each call's ordering kernel rewrites it: calls
+ * whose device work overlaps on one GPU (different streams, threads or
+ * contexts) race; serialize them, e.g. on one stream. */
+int pmh_hash_sets_noalloc(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                          uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
+                          uint64_t* out_keys, void* stream);
 
 /* Same result with one kernel launch per set (the plain form). */
 int pmh_hash_sets_plain(pmh_ctx* ctx, const uint64_t* ids, const double* weights,

@@ -97,6 +97,13 @@ struct HashArgs {
   uint64_t* points;          // optional: points generated (profiling), or null
 };
 
+// The static work buffer of the no-allocation entry point: at most
+// kScratchSets sets per call; scratch_work fills *out with its parts on
+// `device` (which must be current) and *cap with kScratchSets.
+constexpr uint32_t kScratchSets = 1u << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_work(int device, WorkArgs* out, uint64_t* cap);
+
 // launchers (pmh_kernels.hip)
 hipError_t launch_init_tables(int variant, uint32_t m, Tables t, hipStream_t s);
 hipError_t launch_order(const uint64_t* off, uint64_t num_sets, uint32_t split_log2, const WorkArgs& w,

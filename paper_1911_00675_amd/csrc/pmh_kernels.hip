@@ -31,6 +31,8 @@
 
 #include <float.h>
 
+#include <mutex>
+
 #include "pmh_internal.h"
 
 namespace pmh {
@@ -1716,6 +1718,47 @@ __global__ void k_debug_scan(int what, const uint64_t* in_u, uint64_t* out_u, ui
 }
 
 }  // namespace
+
+// ------------------------------------------------------- static work buffer
+// Work list, counters and split-set state of pmh_hash_sets_noalloc, for
+// callers that cannot allocate: batches of at most kScratchSets sets.  Laid
+// out as WorkBuf expects: 8 u32 (counters, meta) at offset 0, order u32[max]
+// at 256, big_prefix u32[max + 1] after it, big_state u64[max] 256-aligned
+// after that.  Every field a launch reads is written by k_order first.
+constexpr size_t kScratchOrder = 256;
+constexpr size_t kScratchPrefix = kScratchOrder + (size_t)kScratchSets * 4;
+constexpr size_t kScratchState = (kScratchPrefix + ((size_t)kScratchSets + 1) * 4 + 255) & ~(size_t)255;
+constexpr size_t kScratchBytes = kScratchState + (size_t)kScratchSets * 8;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The array's device address on `device` (current when called), looked up
+// once per device: every device holds its own copy at its own address, and
+// the host-side name of the array is no device address.
+hipError_t scratch_work(int device, WorkArgs* out, uint64_t* cap) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      if (!p) return hipErrorInvalidSymbol;
+      addr[device] = p;
+    }
+    base = static_cast<unsigned char*>(addr[device]);
+  }
+  uint32_t* small = reinterpret_cast<uint32_t*>(base);
+  out->order = reinterpret_cast<uint32_t*>(base + kScratchOrder);
+  out->counter = small;
+  out->meta = small + 4;
+  out->big_prefix = reinterpret_cast<uint32_t*>(base + kScratchPrefix);
+  out->big_state = reinterpret_cast<uint64_t*>(base + kScratchState);
+  *cap = kScratchSets;
+  return hipSuccess;
+}
 
 // ------------------------------------------------------------------ launchers
 uint32_t batch_size(int waves) { return kEpt * (uint32_t)waves * 64; }

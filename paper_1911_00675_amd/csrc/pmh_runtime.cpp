@@ -192,6 +192,7 @@ const char* pmh_status_str(int st) {
     case PMH_ERR_OOM: return "out of memory";
     case PMH_ERR_BUSY: return "serving queue full";
     case PMH_ERR_NOT_READY: return "request not finished";
+    case PMH_ERR_SCRATCH_LIMIT: return "batch exceeds the no-allocation work buffer (at most 2^20 sets)";
     default: return "unknown status";
   }
 }
@@ -268,6 +269,7 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   if (!rc && hipMalloc(&c->stats, 24 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_OOM;
   if (!rc && hipMemset(c->stats, 0, 24 * sizeof(uint64_t)) != hipSuccess) rc = PMH_ERR_DEVICE;
 #endif
+  if (!rc && scratch_work(dev, &c->scratch, &c->scratch_cap) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && launch_init_tables(variant, m, c->t, nullptr) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) rc = PMH_ERR_DEVICE;
@@ -354,6 +356,31 @@ int pmh_hash_sets(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64
     c->tnext++;
   }
   return enqueue_batched(c, a, &c->work, (hipStream_t)stream, 0, 0, ev0, ev1);
+}
+
+int pmh_hash_sets_noalloc(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off,
+                          uint64_t num_sets, uint32_t* idx, double* val, uint64_t* id, uint64_t* keys,
+                          void* stream) {
+  int rc = check_hash_args(c, ids, w, off, num_sets);
+  if (rc || num_sets == 0) return rc;
+  if (num_sets > c->scratch_cap) return PMH_ERR_SCRATCH_LIMIT;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  // a view of the device's static array, found at pmh_init; never freed
+  WorkBuf wb;
+  wb.order = c->scratch.order;
+  wb.small = c->scratch.counter;
+  wb.big_prefix = c->scratch.big_prefix;
+  wb.big_state = c->scratch.big_state;
+  wb.cap = c->scratch_cap;
+  HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &wb);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->tnext < c->tcount) {
+    ev0 = c->tev[2 * c->tnext];
+    ev1 = c->tev[2 * c->tnext + 1];
+    c->tnext++;
+  }
+  return enqueue_batched(c, a, &wb, (hipStream_t)stream, 0, 0, ev0, ev1);
 }
 
 int pmh_hash_sets_binary(pmh_ctx* c, const uint64_t* ids, const uint64_t* off, uint64_t num_sets, uint32_t* idx,

@@ -68,6 +68,8 @@ struct pmh_ctx {
   uint64_t* stats = nullptr;  // event counters of the statistics build
   pmh::WorkBuf work;
   pmh::WorkBuf gwork;  // the cached graph's own work buffer
+  pmh::WorkArgs scratch{};  // the device's static work buffer (not owned; pmh_hash_sets_noalloc)
+  uint64_t scratch_cap = 0;
   uint32_t imax = 0;   // ProbMinHash1/3 stream cap
   pmh::Tuning tune;
   uint64_t tune_version = 0;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpmh.so")
 
 PMH_OK, PMH_ERR_ARG, PMH_ERR_M_RANGE, PMH_ERR_VARIANT_M, PMH_ERR_WEIGHT = 0, 1, 2, 3, 4
 PMH_ERR_SET_TOO_LARGE, PMH_ERR_DEVICE, PMH_ERR_OOM, PMH_ERR_BUSY, PMH_ERR_NOT_READY = 5, 6, 7, 8, 9
+PMH_ERR_SCRATCH_LIMIT = 10
 IDX_EMPTY = 0xFFFFFFFF
 KEY_EMPTY = 0xFFFFFFFFFFFFFFFF
 
@@ -38,6 +39,7 @@ SIGNATURES = {
     "pmh_bbit_pack": (_i32, [_vp, _u64, _u32, _u32, _vp, _vp]),
     "pmh_bbit_allpairs": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp]),
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
+    "pmh_hash_sets_noalloc": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_graph": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_get_status": (_i32, [_vp, _vp]),
     "pmh_timing_begin": (_i32, [_vp, _i32]),
@@ -208,8 +210,9 @@ class Context:
                   stream=None, outputs=("idx", "val", "id", "keys")) -> Signatures:
         """Signatures of a CSR batch of device tensors (ids int64/uint64,
         weights float64, offsets int64/uint64 with num_sets+1 entries).
-        mode: "batched", "plain", "graph" (ProbMinHash of the context's
-        variant), "pminhash" (P-MinHash with the context's seed and m) or
+        mode: "batched", "plain", "graph", "noalloc" (ProbMinHash of the
+        context's variant; "noalloc" takes its work buffer from the library's
+        static array, at most 2^20 sets), "pminhash" (P-MinHash with the context's seed and m) or
         "binary" (the unit-weight specialisation of the context's variant;
         weights must be None)."""
         torch = _torch()
@@ -227,6 +230,7 @@ class Context:
             _check(rc, "pmh_hash_sets_binary")
             return out
         fn = {"batched": lib().pmh_hash_sets, "plain": lib().pmh_hash_sets_plain,
+              "noalloc": lib().pmh_hash_sets_noalloc,
               "graph": lib().pmh_hash_sets_graph, "pminhash": lib().pmh_pminhash_sets}[mode]
         rc = fn(self._c, _dptr(ids, i64, "ids"), _dptr(weights, (torch.float64,), "weights"),
                 _dptr(offsets, i64, "offsets"), num_sets,
