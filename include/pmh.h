@@ -223,7 +223,8 @@ int pmh_get_tuning(const pmh_ctx* ctx, pmh_tuning* t);
  *   redraws       redraws of Lemire's bounded integers (0..8, default 8);
  *   lemire_floor  validation only: draws whose low product half lies below it
  *                 are redrawn as well, which forces the redraw path (labels
- *                 are then no longer uniform); 0 in normal use.
+ *                 are then no longer uniform); a multiple of 16, 0 in normal
+ *                 use.
  * Applies to later calls of every hashing entry point of the context
  * (P-MinHash has no such loops).  Returns PMH_ERR_ARG for values out of
  * range. */

@@ -30,8 +30,9 @@ struct Tables {
   double* ltab;   // [512]: stream-logarithm cells (inv_j, -log inv_j), then (inv_j, -log 2 inv_j)
   // Loop caps (Sec. 3 advises bounding the generators' loops; part of the
   // result's definition): proposals of the truncated-exponential sampler
-  // (1..32), Lemire redraws (0..8) and a validation-only floor that forces
-  // redraws of draws whose low product half lies below it (0: off).
+  // (1..32), Lemire redraws (0..8) and a validation-only floor (a multiple of
+  // 16) that forces redraws of draws whose low product half lies below it
+  // (0: off).
   uint32_t te_rounds;
   uint32_t redraws;
   uint32_t lemire_floor;

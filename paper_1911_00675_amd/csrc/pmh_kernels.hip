@@ -41,13 +41,18 @@ namespace {
 constexpr double kLn2Hi = 0x1.62e42fefa0000p-1;  // ln 2 rounded to 36 bits
 constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
 // Lane-mode Fisher-Yates steps kept in registers: ProbMinHash2 16 (3 waves
-// per SIMD), ProbMinHash4 4 (its per-step constants, the binary-weight branch
-// and the chain-mode tables leave room for no more at 3 waves per SIMD).
-// Measured at m = 1024, 2,000 sets of 3,000 elements with the earlier
-// readlane search in chain mode: 11.0 -> 1.7 ms (ProbMinHash2, 16 steps
-// against 4), 13.2 -> 8.4 ms (ProbMinHash4, 6 against 4).
-template <int V>
-constexpr uint32_t kFyLaneSteps = V == 4 ? 4 : 16;
+// per SIMD).  ProbMinHash4 16 in one- and two-wave workgroups, as a rolled
+// loop (the step index is wave-uniform, so the register array is indexed in
+// place: 178 VGPRs, 2 waves per SIMD; unrolled, 8 steps took 185 and 16
+// took 278), but 4 unrolled steps in four-wave workgroups (168 VGPRs), where
+// the m keys in LDS (m > 1536) bound the occupancy anyway and elements need
+// hundreds of points.  Measured: mixed batch with unit weights (m = 1024)
+// ProbMinHash4 25.0 -> 14.0 ms with 16 steps; the skewed batch (m = 4096,
+// four waves) went 14.1 -> 15.1 ms with 16 and keeps 4.
+template <int V, int NW>
+constexpr uint32_t kFyLaneSteps = V == 4 && NW == 4 ? 4 : 16;
+template <int V, int NW>
+constexpr bool kFyLaneRolled = V == 4 && NW != 4;
 constexpr uint32_t kEpt = 2;                     // elements per thread per batch
 // Per-wave tables that resolve the dependencies of a chain-mode tile of 64
 // Fisher-Yates steps (ProbMinHash2/4): win[r] = 1 + the latest step of the
@@ -242,9 +247,11 @@ __device__ __forceinline__ double trunc_exp(uint64_t w0, uint64_t pb, double lam
 
 // Redraws of Lemire's method: a draw whose low product half lies below
 // (2^32 - s) mod s (or below the validation floor) is biased and takes the
-// low half of the next word of slots 1..redraws.
-__device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_t s, uint64_t prod,
-                                                           uint32_t redraws, uint32_t floor) {
+// low half of the next word of slots 1..redraws.  capw = floor | redraws
+// (the floor is a multiple of 16, redraws <= 8): one argument of the call,
+// which keeps ProbMinHash4 within 168 VGPRs (3 waves per SIMD).
+__device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_t s, uint64_t prod, uint32_t capw) {
+  const uint32_t floor = capw & ~15u, redraws = capw & 15u;
   uint32_t thr = (0u - s) % s;
   thr = thr < floor ? floor : thr;
   uint32_t lo = (uint32_t)prod;
@@ -256,13 +263,12 @@ __device__ __attribute__((noinline)) uint64_t lemire_redraw(uint64_t pb, uint32_
   return prod;
 }
 // Uniform integer in [0, s) (Lemire's multiply-shift with rejection) from the
-// low half of the point's word 0.  The threshold is below s (and below the
-// floor), so a low half of at least max(s, floor) needs no redraw.
+// low half of the point's word 0.  The threshold is below s and below the
+// floor, so a low half of at least s | floor (>= both) needs no redraw.
 __device__ __forceinline__ uint32_t lemire(uint64_t w0, uint64_t pb, uint32_t s, const Tables& t) {
   const uint64_t x = w0 & 0xFFFFFFFFull;
   uint64_t prod = x * (uint64_t)s;
-  const uint32_t lim = s > t.lemire_floor ? s : t.lemire_floor;
-  if ((uint32_t)prod < lim) prod = lemire_redraw(pb, s, prod, t.redraws, t.lemire_floor);
+  if ((uint32_t)prod < (s | t.lemire_floor)) prod = lemire_redraw(pb, s, prod, t.lemire_floor | t.redraws);
   return (uint32_t)(prod >> 32);
 }
 
@@ -451,7 +457,7 @@ __device__ __forceinline__ uint32_t first_index(double w, double Tprev, uint32_t
 // ------------------------------------------------------------- lane mode
 // Returns after the element's points below R.T are applied, or after pushing
 // the element to a chain queue.
-template <int V>
+template <int V, int NW>
 __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint32_t p, double winv,
                                           uint64_t K, uint64_t kmax, uint64_t* keys, Shared& sm,
                                           ChainEntry* q, int budget, uint32_t i0) {
@@ -509,10 +515,12 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
     // touched slots kept in registers (step s wrote value tr[s] >> 16 into
     // slot tr[s] & 0xFFFF; m <= 2^14); longer streams restart in chain mode,
     // whose 64-step tiles cost far more per point for short streams.
-    uint32_t tr[kFyLaneSteps<V>];
+    constexpr uint32_t kSteps = kFyLaneSteps<V, NW>;
+    constexpr int kUnroll = kFyLaneRolled<V, NW> ? 1 : (int)kSteps;
+    uint32_t tr[kSteps];
     uint64_t tacc = 0;
-#pragma unroll
-    for (uint32_t step = 0; step < kFyLaneSteps<V>; ++step) {
+#pragma unroll kUnroll
+    for (uint32_t step = 0; step < kSteps; ++step) {
       const uint32_t i = step + 1;
       if (i > m) return (int)step;
       const uint64_t pb = pbase(K, i);
@@ -537,7 +545,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
       const uint32_t j = (i - 1) + lemire(w0, pb, m - i + 1, t);
       uint32_t l = j, v = i - 1;
-#pragma unroll
+#pragma unroll kUnroll
       for (uint32_t s = 0; s < step; ++s) {
         const uint32_t sj = tr[s] & 0xFFFFu, sv = tr[s] >> 16;
         if (sj == j) l = sv;
@@ -549,7 +557,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       if (i == m) return (int)step + 1;
     }
     push_long(sm, q, p, 1, 0);
-    return (int)kFyLaneSteps<V>;
+    return (int)kSteps;
   }
 }
 
@@ -967,7 +975,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
       }
       const double winv = 1.0 / w;
       const uint64_t K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
-      const int steps = lane_elem<V>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget, i0);
+      const int steps = lane_elem<V, NW>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget, i0);
 #ifdef PMH_STATS
       // wave-level cost of this element slot: the longest lane
       int mx = steps;

@@ -541,7 +541,8 @@ int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
 }
 
 int pmh_set_caps(pmh_ctx* c, uint32_t imax, uint32_t te_rounds, uint32_t redraws, uint32_t lemire_floor) {
-  if (!c || imax > kImaxMax || te_rounds < 1 || te_rounds > kTeRoundsMax || redraws > kRedrawsMax)
+  if (!c || imax > kImaxMax || te_rounds < 1 || te_rounds > kTeRoundsMax || redraws > kRedrawsMax ||
+      (lemire_floor & 15u))
     return PMH_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->mu);
   c->imax = imax ? imax : imax_for(c->m);

@@ -124,7 +124,7 @@ def _halves(b):
 
 def test_caps_arguments(pmh):
     ctx = pmh.Context(SEED, 16, 3)
-    for bad in ((0, 0, 8, 0), (0, 33, 8, 0), (0, 32, 9, 0), (1 << 24, 32, 8, 0)):
+    for bad in ((0, 0, 8, 0), (0, 33, 8, 0), (0, 32, 9, 0), (1 << 24, 32, 8, 0), (0, 32, 8, 17)):
         with pytest.raises(pmh.PmhError):
             ctx.set_caps(*bad)
     ctx.set_caps((1 << 24) - 1, 32, 8, 0)
