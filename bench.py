@@ -5,12 +5,20 @@ One step hashes the mixed-size workload (100,000 weighted sets, sizes
 log-uniform in [1, 10^4], 20% of ids from a shared pool of 10^6, Pareto(1.5)
 weights normalised per set, ~1.09e8 elements) with ProbMinHash1 and with
 ProbMinHash3 in the batched persistent launch, inputs resident in HBM.
-Also reported on the same inputs: the one-launch-per-set (plain) form, p50 /
-p99 / p99.9 latency of the continuous-batching server under Poisson arrivals
-at 50k requests/s (ProbMinHash3, m = 1024, sizes log-uniform in [10, 10^5]),
-the roofline of the dominant kernel and the CPU reference on host cores.
+Also reported: the one-launch-per-set (plain) form on the same inputs; the
+plain workload of 1,000 sets x 100 elements at m = 256; p50 / p99 / p99.9
+latency of the continuous-batching server under Poisson arrivals at 50k
+requests/s (ProbMinHash3, m = 1024, sizes log-uniform in [10, 10^5], 20,000
+warm-up and 200,000 measured requests); 10^6 sets x 1,000 Zipf-popular ids at
+m = 4096 (ProbMinHash1 vs ProbMinHash3, ten launches of 10^5 sets) with
+all-pairs counting over its first 20,000 signatures; the heavy-skew batch for
+all four variants with their rooflines; the P-MinHash break-even study;
+binary weights; incremental updates; the roofline of the dominant kernel and
+the CPU reference on host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+    PMH_LIB=stats python bench.py --points-summary   # writes the committed
+        points-generated summary with the statistics build (libpmh_stats.so)
 """
 import argparse
 import json
@@ -34,8 +42,12 @@ VARIANTS = (1, 3)
 # hash, value, key, label and one LDS min (ProbMinHash1 62 with the Exp(1)
 # logarithm and the fixed-point step, ProbMinHash3 33 with the
 # truncated-exponential fast path).
-OPS_PER_ELEMENT = {1: 32 + 62, 3: 32 + 33}
-OPS_PER_POINT = {1: 62, 3: 33}
+# ProbMinHash2/4 add to ProbMinHash1/3 what probe kernels of one point
+# differ by in the compiled ISA: the beta_i multiply and the Fisher-Yates
+# step's address arithmetic (its table reads and write are LDS instructions):
+# 3 and 1 VALU instructions.
+OPS_PER_ELEMENT = {1: 32 + 62, 2: 32 + 65, 3: 32 + 33, 4: 32 + 34}
+OPS_PER_POINT = {1: 62, 2: 65, 3: 33, 4: 34}
 # P-MinHash: VALU instructions per (element, component) pair in its inner loop
 # (word hash, Exp(1) by the stream logarithm, scaling, key, running minimum),
 # counted in the compiled gfx950 ISA of k_pmin.
@@ -52,6 +64,7 @@ def harmonic(n):
 
 KERNEL_SOURCES = ("paper_1911_00675_amd/csrc/pmh_kernels.hip", "paper_1911_00675_amd/csrc/pmh_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hash_persistent_mixed_sizes_m1024_traffic.json")
+POINTS_FILE = os.path.join(ROOT, "profiles", "k_hash_persistent_points.json")
 
 
 def kernel_source_sha():
@@ -85,6 +98,118 @@ def measured_traffic(variant, num_sets):
             f"(copy calibration), {os.path.relpath(TRAFFIC_FILE, ROOT)}")
 
 
+def committed_points():
+    """Points generated per set, from the committed statistics-build summary,
+    or None when the kernel sources changed since it was taken."""
+    try:
+        with open(POINTS_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    return t
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def traffic_summary(fetch_dir, write_dir, out_path):
+    """HBM bytes of the hash kernel from two rocprofv3 runs of
+    `bench.py --profile --steps 1 --warmup 0 --copy-calibrate` (FETCH_SIZE,
+    then WRITE_SIZE, csv output): per-dispatch KiB of the last dispatch of each
+    variant's k_hash_persistent, scaled by the counters' reading for the 1 GiB
+    device copy; written with the kernel sources' hash."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    key = (int(row["Dispatch_Id"]), row["Kernel_Name"], int(row["Grid_Size"]))
+                    vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+        return vals
+
+    out = {"kernel": "k_hash_persistent", "workload": "mixed_sizes (100,000 sets, 1.089e8 elements), m=1024",
+           "num_sets": 100000, "kernel_source_sha256": kernel_source_sha(),
+           "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out> "
+                        "-o run -- python3 <repo>/bench.py --profile --steps 1 --warmup 0 --copy-calibrate",
+                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out> "
+                        "-o run -- python3 <repo>/bench.py --profile --steps 1 --warmup 0 --copy-calibrate",
+                        "python bench.py --traffic-summary <fetch out> <write out>"],
+           "kernels": {}}
+    cal = {}
+    for counter, d, key in (("FETCH_SIZE", fetch_dir, "fetch"), ("WRITE_SIZE", write_dir, "write")):
+        vals = per_dispatch(d, counter)
+        # the calibration copies: the copy dispatches of the largest grid (the
+        # uploads of the inputs are copies too, of other sizes)
+        grid = max(g for (i, k, g) in vals if "copyBuffer" in k)
+        copies = [v for (i, k, g), v in sorted(vals.items()) if "copyBuffer" in k and g == grid]
+        cal[f"copy_{key}_kib"] = float(np.mean(copies))
+        for variant in (1, 3):
+            ks = [v for (i, k, g), v in sorted(vals.items()) if f"k_hash_persistent<{variant}," in k]
+            out["kernels"].setdefault(f"pmh{variant}", {})[f"{key}_kib"] = ks[-1]
+    gib = float(1 << 30)
+    out["calibration"] = {"copy_bytes": int(gib), **cal, "fetch_factor": gib / 1024.0 / cal["copy_fetch_kib"],
+                          "write_factor": gib / 1024.0 / cal["copy_write_kib"]}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+
+
+def points_summary(out_path):
+    """Statistics build (PMH_LIB=stats): points generated per set and
+    variant on the mixed and skewed batches, written to POINTS_FILE."""
+    import ctypes
+    import torch
+    from paper_1911_00675_amd import pmh, workloads as W
+    assert pmh.LIB_PATH.endswith("libpmh_stats.so"), "run with PMH_LIB=stats"
+    L = pmh.lib()
+    L.pmh_stats_read.restype = ctypes.c_int
+    L.pmh_stats_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    out = {"kernel_source_sha256": kernel_source_sha(),
+           "command": "python -m paper_1911_00675_amd.build --stats && PMH_LIB=stats python bench.py --points-summary",
+           "counters": "lane-mode, mini-chain and chain points per set (statistics build of the same kernels)",
+           "workloads": {}}
+    for name, gen, m in (("mixed_sizes", W.mixed_sizes, 1024), ("skewed", W.skewed, 4096)):
+        b = gen()
+        ids, w, off = pmh.to_device(b.ids), pmh.to_device(b.weights), pmh.to_device(b.offsets)
+        q = m * harmonic(m)
+        nz = int((b.sizes() > 0).sum())
+        res = {"m": m, "num_sets": b.num_sets, "m_H_m": q}
+        for v in (1, 2, 3, 4):
+            ctx = pmh.Context(SEED, m, v)
+            o = ctx.alloc_outputs(b.num_sets, ("idx", "val"))
+            ctx.hash_sets(ids, w, off, out=o)
+            buf = np.zeros(24, dtype=np.uint64)
+            torch.cuda.synchronize()
+            L.pmh_stats_read(ctx._c, buf.ctypes.data, 1)
+            ctx.hash_sets(ids, w, off, out=o)
+            torch.cuda.synchronize()
+            L.pmh_stats_read(ctx._c, buf.ctypes.data, 1)
+            pts = int(buf[3]) + int(buf[7]) + int(buf[10])  # lane, mini-chain and chain points
+            res[f"pmh{v}"] = {"points_per_set": pts / nz, "over_m_H_m": pts / (nz * q),
+                              "rounds_per_item": int(buf[1]) / max(int(buf[0]), 1)}
+            ctx.close()
+        out["workloads"][name] = res
+        log(f"points: {name} {res}")
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,8 +224,17 @@ def parse():
     ap.add_argument("--no-binary", action="store_true")
     ap.add_argument("--no-update", action="store_true")
     ap.add_argument("--no-skewed", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=6000)
-    ap.add_argument("--cpu-sets", type=int, default=3000)
+    ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=200_000, help="measured requests (after 20,000 warm-up)")
+    ap.add_argument("--serving-pool", type=int, default=20_000, help="distinct requests the arrivals draw from")
+    ap.add_argument("--large-chunks", type=int, default=10, help="launches of 10^5 sets of the 10^6-set workload")
+    ap.add_argument("--cpu-sets", type=int, default=20_000)
+    ap.add_argument("--cpu-single-sets", type=int, default=2_000)
+    ap.add_argument("--points-summary", nargs="?", const=POINTS_FILE, default=None, metavar="OUT",
+                    help="statistics build only: write the points-generated summary (default: profiles/)")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    help="write the HBM traffic summary from two rocprofv3 counter runs")
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no plain/serving/cpu legs")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run a 1 GiB device-to-device copy (3 times) to calibrate HBM byte counters")
@@ -117,9 +251,15 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.points_summary:
+        points_summary(args.points_summary)
+        return
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
     if args.profile:
         args.no_plain = args.no_serving = args.no_cpu = args.no_break_even = args.no_allpairs = True
-        args.no_binary = args.no_update = args.no_skewed = True
+        args.no_binary = args.no_update = args.no_skewed = args.no_small = args.no_large = True
     import torch
     from paper_1911_00675_amd import pmh, workloads as W
 
@@ -195,6 +335,16 @@ def main():
         "hbm_algorithmic_GBps": hbm_bytes / (launch_ms[dom] * 1e-3) / 1e9,
         "hbm_frac": hbm_bytes / (launch_ms[dom] * 1e-3) / PEAK_HBM,
     }
+    pts = committed_points()
+    if pts and pts["workloads"].get("mixed_sizes", {}).get("num_sets") == S:
+        wm = pts["workloads"]["mixed_sizes"]
+        roofline["points_generated"] = {
+            f"pmh{v}": {"per_set": wm[f"pmh{v}"]["points_per_set"], "over_m_H_m": wm[f"pmh{v}"]["over_m_H_m"]}
+            for v in (1, 2, 3, 4)}
+        roofline["points_generated_note"] = f"statistics build, {os.path.relpath(POINTS_FILE, ROOT)}"
+    else:
+        roofline["points_generated"] = None
+        roofline["points_generated_note"] = "kernel changed since the points summary was taken"
 
     # ------------------------------------------------------------ plain form
     plain = None
@@ -211,26 +361,58 @@ def main():
                                 "batched_over_plain": pms / launch_ms[v]}
         log(f"plain: {plain}")
 
+    # --------------------------------------------- plain workload, m = 256
+    # 1,000 sets x 100 elements, ProbMinHash1: one launch per set (the form the
+    # workload is quoted in) and one batched launch.
+    small = None
+    if not args.no_small:
+        sb = W.plain_pairs()
+        sctx = pmh.Context(SEED, 256, 1)
+        sd = [pmh.to_device(a) for a in (sb.ids, sb.weights, sb.offsets)]
+        so = sctx.alloc_outputs(sb.num_sets, ("idx", "val"))
+        small = {"num_sets": sb.num_sets, "num_elements": sb.num_elements, "m": 256, "variant": "ProbMinHash1"}
+        for mode in ("plain", "batched"):
+            sctx.hash_sets(*sd, out=so, mode=mode)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                sctx.hash_sets(*sd, out=so, mode=mode)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            small[mode] = {"ms": ms, "elements_per_s": sb.num_elements / (ms * 1e-3),
+                           "components_per_s": sb.num_sets * 256 / (ms * 1e-3)}
+        if sctx.status() != pmh.PMH_OK:
+            raise RuntimeError("plain-workload leg: bad status")
+        small["plain_over_batched"] = small["plain"]["ms"] / small["batched"]["ms"]
+        sctx.close()
+        log(f"small: {small}")
+
     # ------------------------------------------------------------ serving
+    # Poisson arrivals at 50,000 requests/s, 20,000 warm-up then the measured
+    # requests; the arrivals draw their sets from a pool of distinct requests
+    # staged once in pinned host memory (2.4e9 elements of fresh requests
+    # would not fit it), each request copied in, hashed and copied out anew.
     latency = None
     if not args.no_serving:
-        rq = W.serving_requests(num_requests=args.serving_requests)
+        warm = 20_000
+        num = warm + args.serving_requests
+        rq = W.serving_requests(num_requests=args.serving_pool)
+        rng = np.random.default_rng(44)
+        order = rng.integers(0, rq.num_sets, size=num)
+        arrival = np.cumsum(rng.exponential(1.0 / rq.meta["rate"], size=num))
         srv = pmh.Server(ctxs[3], slots=4, slot_elems=1 << 23, slot_sets=4096)
-        # warm-up replay of the first requests (GPU clocks, host threads), then
-        # the measured replay with its first requests dropped as well
-        nw = min(2000, rq.num_sets)
-        srv.replay(rq.ids[:int(rq.offsets[nw])], rq.weights[:int(rq.offsets[nw])], rq.offsets[:nw + 1],
-                   rq.meta["arrival"][:nw])
-        warm = min(1000, rq.num_sets // 4)
-        lat, _, _, wall = srv.replay(rq.ids, rq.weights, rq.offsets, rq.meta["arrival"])
+        lat, wall = srv.replay_indexed(rq.ids, rq.weights, rq.offsets, order, arrival)
         st = srv.stats()
         srv.close()
         lm = lat[warm:] * 1e6
+        n_el = float(rq.sizes()[order].sum())
         latency = {"p50_us": float(np.percentile(lm, 50)), "p99_us": float(np.percentile(lm, 99)),
-                   "p999_us": float(np.percentile(lm, 99.9)), "requests": int(rq.num_sets - warm),
-                   "offered_req_per_s": rq.meta["rate"], "achieved_req_per_s": rq.num_sets / wall,
-                   "elements_per_s": rq.num_elements / wall, "variant": "ProbMinHash3", "m": M,
-                   "server": st}
+                   "p999_us": float(np.percentile(lm, 99.9)), "max_us": float(lm.max()),
+                   "requests": int(num - warm), "warmup_requests": warm, "distinct_requests": rq.num_sets,
+                   "offered_req_per_s": rq.meta["rate"], "achieved_req_per_s": num / wall,
+                   "elements_per_s": n_el / wall, "variant": "ProbMinHash3", "m": M, "server": st}
         log(f"serving: {latency}")
 
     # ------------------------------------------- P-MinHash break-even study
@@ -285,40 +467,92 @@ def main():
         }
         log(f"break-even: {break_even}")
 
-    # -------------------------------------------------- all-pairs estimation
-    # Eq. (3) over every pair of 20,000 signatures of m = 4096 components
-    # (2e8 pairs): 32-bit fingerprints of the element ids, and the b-bit
-    # reductions of Sec. 1.3 (packed, b = 1 and 4).  Random ids stand in for
-    # signatures: the kernels' work does not depend on the values.
+    # ------------------------------- 10^6 sets x 1,000 ids, m = 4096, all pairs
+    # The Zipf-popularity workload in ten launches of 10^5 sets (each 10^8
+    # elements), ProbMinHash1 and ProbMinHash3; the sets are generated by a
+    # process pool in independently seeded blocks while the GPU runs.  Then
+    # eq. (3) over every pair of the first 20,000 ProbMinHash1 signatures:
+    # 32-bit fingerprints of the element ids, and the b-bit reductions of
+    # Sec. 1.3 (b = 1 and 4).
+    large = None
     allpairs = None
-    if not args.no_allpairs:
-        ka, ma = 20_000, 4096
-        rng = np.random.default_rng(SEED)
-        aid = torch.from_numpy(rng.integers(1, 2**62, size=(ka, ma), dtype=np.int64)).cuda()
-        afp = (aid & 0xFFFFFFFF).to(torch.int32)
+    if not args.no_large:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        m5, chunk = 4096, 100_000
+        per = chunk // W.LARGE_BLOCK
+        lctx = {v: pmh.Context(SEED, m5, v) for v in VARIANTS}
+        louts = {v: lctx[v].alloc_outputs(chunk, ("idx", "val", "id")) for v in VARIANTS}
+        kern = {v: [] for v in VARIANTS}
+        calls = {v: [] for v in VARIANTS}
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+        t_gen = time.time()
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            pending = ex.map(W.large_block, [5] * (args.large_chunks * per), range(args.large_chunks * per))
+            for c in range(args.large_chunks):
+                parts = [next(pending) for _ in range(per)]
+                d = [pmh.to_device(np.concatenate([p.ids for p in parts])),
+                     pmh.to_device(np.concatenate([p.weights for p in parts])),
+                     pmh.to_device(np.arange(chunk + 1, dtype=np.uint64) * np.uint64(1000))]
+                del parts
+                for v in VARIANTS:
+                    if c == 0:  # first call of the context: work buffers
+                        lctx[v].hash_sets(*d, out=louts[v])
+                    torch.cuda.synchronize()
+                    lctx[v].timing_begin(1)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    lctx[v].hash_sets(*d, out=louts[v])
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    kern[v].append(float(lctx[v].timing_read(1)[0]))
+                    calls[v].append(e0.elapsed_time(e1))
+                    if lctx[v].status() != pmh.PMH_OK:
+                        raise RuntimeError(f"large leg PMH{v}: bad status")
+                if c == 0 and not args.no_allpairs:
+                    ka = 20_000
+                    sig_id = louts[1].id[:ka].contiguous()
+                    idx1 = louts[1].idx[:ka]
+                    afp = torch.where(idx1 == -1, torch.zeros_like(idx1), (sig_id & 0xFFFFFFFF).to(torch.int32))
+                    afp = afp.contiguous()
 
-        def timed(fn, reps=3):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
-                fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / reps
+                    def timed(fn, reps=3):
+                        fn()
+                        torch.cuda.synchronize()
+                        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        a0.record(stream)
+                        for _ in range(reps):
+                            fn()
+                        a1.record(stream)
+                        torch.cuda.synchronize()
+                        return a0.elapsed_time(a1) / reps
 
-        allpairs = {"signatures": ka, "m": ma, "pairs": ka * ka,
-                    "fp32_ms": timed(lambda: pmh.allpairs_counts(afp))}
-        for bb in (1, 4):
-            packed = pmh.bbit_pack(aid, bb)
-            allpairs[f"b{bb}_pack_ms"] = timed(lambda: pmh.bbit_pack(aid, bb))
-            allpairs[f"b{bb}_ms"] = timed(lambda: pmh.bbit_allpairs(packed, ma, bb))
-        allpairs["component_compares_per_s"] = {
-            k.replace("_ms", ""): ka * ka * ma / (v * 1e-3) for k, v in allpairs.items()
-            if k.endswith("_ms") and "pack" not in k}
-        del aid, afp
-        log(f"allpairs: {allpairs}")
+                    allpairs = {"signatures": ka, "m": m5, "pairs": ka * ka,
+                                "source": "first 20,000 ProbMinHash1 signatures of the 10^6-set workload",
+                                "fp32_ms": timed(lambda: pmh.allpairs_counts(afp))}
+                    for bb in (1, 4):
+                        packed = pmh.bbit_pack(sig_id, bb)
+                        allpairs[f"b{bb}_pack_ms"] = timed(lambda: pmh.bbit_pack(sig_id, bb))
+                        allpairs[f"b{bb}_ms"] = timed(lambda: pmh.bbit_allpairs(packed, m5, bb))
+                        del packed
+                    allpairs["component_compares_per_s"] = {
+                        k.replace("_ms", ""): ka * ka * m5 / (v_ * 1e-3) for k, v_ in allpairs.items()
+                        if k.endswith("_ms") and "pack" not in k}
+                    del afp, sig_id
+                    log(f"allpairs: {allpairs}")
+                del d
+        n5 = args.large_chunks * chunk * 1000
+        large = {"num_sets": args.large_chunks * chunk, "num_elements": n5, "m": m5, "launches": args.large_chunks,
+                 "wall_s_incl_generation": time.time() - t_gen}
+        for v in VARIANTS:
+            tk, tc = float(np.sum(kern[v])), float(np.sum(calls[v]))
+            large[f"pmh{v}"] = {"kernel_ms_per_launch": tk / args.large_chunks, "call_ms_per_launch": tc / args.large_chunks,
+                                "elements_per_s": n5 / (tk * 1e-3),
+                                "components_per_s": args.large_chunks * chunk * m5 / (tk * 1e-3),
+                                "elements_per_s_whole_calls": n5 / (tc * 1e-3)}
+            lctx[v].close()
+        del louts
+        log(f"large: {large}")
 
     # ------------------------------------------- binary-weight specialisations
     # Sec. 2.9: the same mixed batch without weights (every weight 1), each
@@ -408,8 +642,17 @@ def main():
             kms = float(np.mean(sc.timing_read(2)))
             if sc.status() != pmh.PMH_OK:
                 raise RuntimeError(f"skewed leg PMH{v}: status {sc.status()}")
+            q4 = 4096 * harmonic(4096)
+            ops = sb.num_elements * OPS_PER_ELEMENT[v] + float((sb.sizes() > 0).sum()) * q4 * OPS_PER_POINT[v]
             skewed[f"pmh{v}"] = {"kernel_ms": kms, "elements_per_s": sb.num_elements / (kms * 1e-3),
-                                 "waves": sc.get_tuning().waves}
+                                 "waves": sc.get_tuning().waves,
+                                 "roofline": {"bound": "alu", "achieved": ops / (kms * 1e-3) / 1e12,
+                                              "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
+                                              "frac": ops / (kms * 1e-3) / PEAK_VALU,
+                                              "ops_model": {"per_element": OPS_PER_ELEMENT[v],
+                                                            "per_point": OPS_PER_POINT[v]},
+                                              "hbm_frac": (16.0 * sb.num_elements + 12.0 * sb.num_sets * 4096)
+                                              / (kms * 1e-3) / PEAK_HBM}}
             sc.close()
             del so
         del sids, sw, soff, sb
@@ -420,7 +663,7 @@ def main():
     if not args.no_cpu:
         import oracle
         oracle.build()
-        cores = os.cpu_count() or 1
+        cores = len(os.sched_getaffinity(0))
         samp = b.subset(np.arange(min(args.cpu_sets, S)))
         tc = {}
         for v in VARIANTS:
@@ -428,10 +671,20 @@ def main():
             oracle.sign_batch(v, SEED, M, samp.ids, samp.weights, samp.offsets, nthreads=cores)
             tc[v] = time.perf_counter() - c0
         cpu_val = len(VARIANTS) * samp.num_elements / sum(tc.values())
+        one = b.subset(np.arange(min(args.cpu_single_sets, S)))
+        t1 = {}
+        for v in VARIANTS:
+            c0 = time.perf_counter()
+            oracle.sign_batch(v, SEED, M, one.ids, one.weights, one.offsets, nthreads=1)
+            t1[v] = time.perf_counter() - c0
         cpu = {"value": cpu_val, "unit": "elements/s", "cores": cores, "kind": "oracle",
                "sample": f"first {samp.num_sets} sets ({samp.num_elements} elements) of the same workload, "
-                         f"ProbMinHash1+3 sequential per set, {cores} threads",
-               "seconds": {f"pmh{v}": tc[v] for v in VARIANTS}}
+                         f"ProbMinHash1+3 sequential per set, {cores} threads (one set per task)",
+               "seconds": {f"pmh{v}": tc[v] for v in VARIANTS},
+               "cpu_model": cpu_model(), "compiler": "gcc " + " ".join(oracle.CFLAGS),
+               "single_core": {"value": len(VARIANTS) * one.num_elements / sum(t1.values()), "unit": "elements/s",
+                               "sample": f"first {one.num_sets} sets ({one.num_elements} elements), one thread",
+                               "seconds": {f"pmh{v}": t1[v] for v in VARIANTS}}}
         log(f"cpu: {cpu}")
 
     out = {
@@ -449,7 +702,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain": plain,
+        "plain_small": small,
         "latency": latency,
+        "large_uniform": large,
         "break_even": break_even,
         "allpairs": allpairs,
         "binary": binary,

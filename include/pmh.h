@@ -327,6 +327,15 @@ int pmh_server_fetch(pmh_server* s, uint64_t ticket, uint32_t* idx, double* val,
 int pmh_server_replay(pmh_server* s, const uint64_t* ids, const double* weights, const uint64_t* offsets,
                       uint64_t num, const double* arrival, double* latency, uint32_t* out_idx,
                       uint64_t* out_id, double* wall);
+/* Open-loop replay of num requests drawn from a pool of `pool` distinct
+ * requests (CSR [host] ids, weights, offsets[pool+1]): request r is pool
+ * entry order[r] (order [host] or NULL for r, num <= pool), submitted at
+ * arrival[r] seconds; the pool is staged once in pinned host memory.  Same
+ * outputs and timing as pmh_server_replay, which is this call with the
+ * identity order. */
+int pmh_server_replay_indexed(pmh_server* s, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                              uint64_t pool, const uint64_t* order, uint64_t num, const double* arrival,
+                              double* latency, uint32_t* out_idx, uint64_t* out_id, double* wall);
 /* Counters into out8[8]: [0] batches launched, [1] requests done, [2] max
  * requests in one batch, [3] max concurrent slots busy, [4] requests that
  * waited for a slot; dispatcher timing in microseconds: [5] longest launch

@@ -42,13 +42,14 @@ ERR_OOM = 7
 MODE_SEQUENTIAL, MODE_INTERLEAVED, MODE_BRUTE = 0, 1, 2
 
 
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fPIC"]
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with strict IEEE double semantics (no contraction)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
-            "-fPIC", "-shared", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        subprocess.check_call(["gcc"] + CFLAGS + ["-shared", "-o", tmp, _SRC, "-lm", "-lpthread"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

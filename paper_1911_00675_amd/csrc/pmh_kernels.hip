@@ -542,6 +542,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         else
           x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
       }
+      PMH_STAT(sm, kStLanePts, 1);
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
       const uint32_t j = (i - 1) + lemire(w0, pb, m - i + 1, t);
       uint32_t l = j, v = i - 1;

@@ -531,13 +531,22 @@ int pmh_server_fetch(pmh_server* S, uint64_t ticket, uint32_t* idx, double* val,
 
 int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num,
                       const double* arrival, double* latency, uint32_t* out_idx, uint64_t* out_id, double* wall) {
-  if (!S || !off || !arrival || (num && (!ids || !w))) return PMH_ERR_ARG;
+  return pmh_server_replay_indexed(S, ids, w, off, num, nullptr, num, arrival, latency, out_idx, out_id, wall);
+}
+
+int pmh_server_replay_indexed(pmh_server* S, const uint64_t* ids, const double* w, const uint64_t* off,
+                              uint64_t pool, const uint64_t* order, uint64_t num, const double* arrival,
+                              double* latency, uint32_t* out_idx, uint64_t* out_id, double* wall) {
+  if (!S || !off || !arrival || (pool && (!ids || !w)) || (!order && num > pool)) return PMH_ERR_ARG;
   const uint32_t m = S->ctx->m;
-  for (uint64_t r = 0; r < num; ++r)
+  for (uint64_t r = 0; r < pool; ++r)
     if (off[r + 1] < off[r] || off[r + 1] - off[r] > kMaxSet) return PMH_ERR_ARG;
-  // The requests are pre-generated: stage them once in pinned host memory
+  if (order)
+    for (uint64_t r = 0; r < num; ++r)
+      if (order[r] >= pool) return PMH_ERR_ARG;
+  // The requests are pre-generated: stage the pool once in pinned host memory
   // (before the clock starts) so each batch is DMA'd from there directly.
-  const uint64_t total = num ? off[num] - off[0] : 0;
+  const uint64_t total = pool ? off[pool] - off[0] : 0;
   uint64_t* p_ids = nullptr;
   double* p_w = nullptr;
   const uint64_t* src_ids = nullptr;
@@ -578,10 +587,11 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
   }
   std::vector<Request*> reqs(num);
   for (uint64_t r = 0; r < num; ++r) {
+    const uint64_t e = order ? order[r] : r;  // pool entry of request r
     Request* q = new Request();
-    q->n = (uint32_t)(off[r + 1] - off[r]);
-    q->src_ids = src_ids + (off[r] - off[0]);
-    q->src_w = src_w + (off[r] - off[0]);
+    q->n = (uint32_t)(off[e + 1] - off[e]);
+    q->src_ids = src_ids + (off[e] - off[0]);
+    q->src_w = src_w + (off[e] - off[0]);
     q->dst_idx = out_idx ? out_idx + r * m : nullptr;
     q->dst_id = out_id ? out_id + r * m : nullptr;
     reqs[r] = q;
@@ -591,7 +601,8 @@ int pmh_server_replay(pmh_server* S, const uint64_t* ids, const double* w, const
     const double due = start + arrival[r];
     while (now_s(S->epoch) < due) {
     }
-    submit_internal(S, reqs[r], ids + off[r], w + off[r]);
+    const uint64_t e = order ? order[r] : r;
+    submit_internal(S, reqs[r], ids + off[e], w + off[e]);
   }
   double last = start;
   int rc = PMH_OK;

@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpmh.so")
+# PMH_LIB=stats selects the event-counting build libpmh_stats.so (schedule
+# analysis only; same kernels with counters)
+LIB_PATH = os.path.join(_HERE, "libpmh_stats.so" if os.environ.get("PMH_LIB") == "stats" else "libpmh.so")
 
 PMH_OK, PMH_ERR_ARG, PMH_ERR_M_RANGE, PMH_ERR_VARIANT_M, PMH_ERR_WEIGHT = 0, 1, 2, 3, 4
 PMH_ERR_SET_TOO_LARGE, PMH_ERR_DEVICE, PMH_ERR_OOM, PMH_ERR_BUSY, PMH_ERR_NOT_READY = 5, 6, 7, 8, 9
@@ -57,6 +59,8 @@ SIGNATURES = {
     "pmh_server_submit": (_i32, [_vp, _vp, _vp, _u32, ctypes.POINTER(_u64)]),
     "pmh_server_fetch": (_i32, [_vp, _u64, _vp, _vp, _vp]),
     "pmh_server_replay": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp, _vp, ctypes.POINTER(_dbl)]),
+    "pmh_server_replay_indexed": (_i32, [_vp, _vp, _vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp, _vp,
+                                         ctypes.POINTER(_dbl)]),
     "pmh_server_stats": (_i32, [_vp, _vp]),
     "pmh_server_destroy": (None, [_vp]),
 }
@@ -443,6 +447,25 @@ class Server:
         _check(lib().pmh_server_replay(self._s, vp(ids), vp(w), vp(off), num, vp(arr), vp(lat), vp(idx), vp(idv),
                                        ctypes.byref(wall)), "pmh_server_replay")
         return lat, idx, idv, wall.value
+
+    def replay_indexed(self, ids, weights, offsets, order, arrival):
+        """Open-loop replay of requests drawn from a CSR pool of host requests
+        (request r is pool entry order[r]).  Returns (latency[num] s, wall s);
+        no signatures are copied back."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        order = np.ascontiguousarray(order, dtype=np.uint64)
+        arr = np.ascontiguousarray(arrival, dtype=np.float64)
+        if order.size != arr.size:
+            raise ValueError("order and arrival differ in length")
+        lat = np.zeros(arr.size, dtype=np.float64)
+        wall = ctypes.c_double()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(lib().pmh_server_replay_indexed(self._s, vp(ids), vp(w), vp(off), off.size - 1, vp(order),
+                                               order.size, vp(arr), vp(lat), None, None, ctypes.byref(wall)),
+               "pmh_server_replay_indexed")
+        return lat, wall.value
 
     def stats(self) -> dict:
         o = np.zeros(8, dtype=np.uint64)
