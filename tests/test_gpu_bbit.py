@@ -23,7 +23,7 @@ def pmh():
 
 
 @pytest.mark.parametrize("b", [1, 2, 4, 8, 16])
-@pytest.mark.parametrize("m", [1, 63, 333, 1024])
+@pytest.mark.parametrize("m", [1, 63, 333, 1024, 4096, 16384])
 def test_pack_and_allpairs_bit_exact(pmh, b, m):
     import torch
     print(f"bbit b={b} m={m}", flush=True)
