@@ -535,9 +535,19 @@ def main():
                         allpairs[f"b{bb}_pack_ms"] = timed(lambda: pmh.bbit_pack(sig_id, bb))
                         allpairs[f"b{bb}_ms"] = timed(lambda: pmh.bbit_allpairs(packed, m5, bb))
                         del packed
+                    # the 1-bit reduction fused into the hash kernel's epilogue
+                    # (pmh_hash_sets_bbit) against the same launch without it
+                    fused = louts[1]
+                    lctx[1].hash_sets(*d, out=fused, bbit=1)
+                    torch.cuda.synchronize()
+                    lctx[1].timing_begin(1)
+                    lctx[1].hash_sets(*d, out=fused, bbit=1)
+                    allpairs["b1_fused_hash_kernel_ms"] = float(lctx[1].timing_read(1)[0])
+                    allpairs["hash_kernel_ms"] = kern[1][0]
+                    fused.bbit = None
                     allpairs["component_compares_per_s"] = {
                         k.replace("_ms", ""): ka * ka * m5 / (v_ * 1e-3) for k, v_ in allpairs.items()
-                        if k.endswith("_ms") and "pack" not in k}
+                        if k.endswith("_ms") and "pack" not in k and "kernel" not in k}
                     del afp, sig_id
                     log(f"allpairs: {allpairs}")
                 del d

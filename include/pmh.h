@@ -134,6 +134,19 @@ int pmh_hash_sets_noalloc(pmh_ctx* ctx, const uint64_t* ids, const double* weigh
                           uint64_t num_sets, uint32_t* out_idx, double* out_val, uint64_t* out_id,
                           uint64_t* out_keys, void* stream);
 
+/* pmh_hash_sets with the b-bit reduction of Sec. 1.3 (algorithm "Reduction
+ * to a b-bit signature") computed in the same kernel, as each signature is
+ * finished: out_bbit[num_sets][ceil(m b / 64)] uint64 [device] receives
+ * exactly what pmh_bbit_pack writes for the signatures' ids (component k,
+ * 1-based, keeps the b low bits of mix64(mix64(id) + k * 0x9E3779B97F4A7C15),
+ * id 0 for an empty component; component k-1 at bit (k-1) b, padding zero),
+ * without a second pass over the ids.  b in {1, 2, 4, 8, 16}.  The other
+ * outputs are optional as for pmh_hash_sets (sets are split across
+ * workgroups only when out_keys, out_val or out_id is given). */
+int pmh_hash_sets_bbit(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
+                       uint64_t num_sets, uint32_t b, uint64_t* out_bbit, uint32_t* out_idx, double* out_val,
+                       uint64_t* out_id, uint64_t* out_keys, void* stream);
+
 /* Same result with one kernel launch per set (the plain form). */
 int pmh_hash_sets_plain(pmh_ctx* ctx, const uint64_t* ids, const double* weights,
                         const uint64_t* offsets, uint64_t num_sets, uint32_t* out_idx,

@@ -76,6 +76,8 @@ struct HashArgs {
   double* out_val;           // [num_sets * m] or null
   uint64_t* out_id;          // [num_sets * m] or null
   uint64_t* out_keys;        // [num_sets * m] or null
+  uint64_t* out_bbit;        // [num_sets * ceil(m b / 64)] b-bit reduction (Sec. 1.3) or null
+  uint32_t bbit_b;           // its field width b (1, 2, 4, 8 or 16)
   uint64_t seedhash;
   uint32_t m;
   uint32_t imax;

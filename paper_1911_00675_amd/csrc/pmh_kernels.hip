@@ -1028,7 +1028,7 @@ __device__ __forceinline__ uint64_t seed_key(uint64_t old) { return old == kEmpt
 // keys (LDS) -> (position, value, id) of the set's signature.  Update mode
 // (A.counts): a component whose LDS key still equals its seed keeps the
 // previous key and id; one a new element won takes position base + p.
-template <int NW>
+template <int NW, bool kBbit = false>
 __device__ void epilogue(const HashArgs& A, const Round& R, uint64_t set, const uint64_t* keys, Shared& sm) {
   constexpr int BS = NW * 64;
   const int tid = threadIdx.x;
@@ -1057,13 +1057,36 @@ __device__ void epilogue(const HashArgs& A, const Round& R, uint64_t set, const 
     if (A.out_id && fresh) A.out_id[o + k] = empty ? 0ull : R.ids[pos - base];
   }
   if (A.counts && tid == 0) A.counts[set] = base + R.n;
+  if constexpr (kBbit) {
+    // b-bit reduction (Sec. 1.3) of the finished signature: component k
+    // (0-based) keeps the b low bits of mix64(mix64(z) + (k + 1) phi), z its
+    // element id (0: empty).  A wave's lanes hold consecutive components, so
+    // an OR over aligned groups of 64/b lanes assembles each packed word.
+    // Its own kernel instantiations: inlined into the others it raised
+    // ProbMinHash2's and ProbMinHash4's registers past 3 waves per SIMD.
+    const uint32_t lb = (uint32_t)__builtin_ctz(A.bbit_b);  // log2 b
+    const uint32_t per = 64u >> lb;
+    const uint64_t mask = (1ull << A.bbit_b) - 1ull;
+    const uint64_t words = (((uint64_t)m << lb) + 63) >> 6;
+    for (uint32_t k0 = 0; k0 < m; k0 += BS) {
+      const uint32_t k = k0 + (uint32_t)tid;
+      uint64_t f = 0;
+      if (k < m) {
+        const uint64_t key = keys[k];
+        const uint64_t z = key == kEmptyKey ? 0ull : R.ids[(uint32_t)(key & kPosMask)];
+        f = (mix64(mix64(z) + (uint64_t)(k + 1) * kPhi) & mask) << ((k & (per - 1)) << lb);
+      }
+      for (uint32_t d = 1; d < per; d <<= 1) f |= shfl_xor_u64(f, (int)d);
+      if (k < m && (k & (per - 1)) == 0) A.out_bbit[set * words + (k >> (6 - lb))] = f;
+    }
+  }
   __syncthreads();
 #ifdef PMH_STATS
   if (tid < kStCount && A.points) atomicAdd((unsigned long long*)&A.points[tid], (unsigned long long)sm.st[tid]);
 #endif
 }
 
-template <int V, int NW>
+template <int V, int NW, bool kBbit = false>
 __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
                             uint16_t* fy, const LogCell* lt, Shared& sm) {
   Round R = set_round<NW>(A, set, qcap, lt, sm);
@@ -1088,7 +1111,7 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
   const double W = block_weight_sum<NW>(A, R, 0, R.n, sm);
   if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kmax0, keys, q, fy, sm);
   PMH_TOC(sm, kStCycSet, t_set);
-  epilogue<NW>(A, R, set, keys, sm);
+  epilogue<NW, kBbit>(A, R, set, keys, sm);
 }
 
 // One chunk of a set split across workgroups.  The chunk generates every
@@ -1127,7 +1150,7 @@ __device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uin
 // Completion of a split set: every merged key below the smallest chunk
 // threshold Tmin is final (all points below Tmin were applied); otherwise one
 // unbounded round over the whole set finishes it.  Then the epilogue.
-template <int V, int NW>
+template <int V, int NW, bool kBbit = false>
 __device__ void finish_set(const HashArgs& A, uint64_t set, uint32_t big, uint64_t* keys, ChainEntry* q,
                            uint32_t qcap, uint16_t* fy, const LogCell* lt, Shared& sm) {
   const int tid = threadIdx.x;
@@ -1142,7 +1165,7 @@ __device__ void finish_set(const HashArgs& A, uint64_t set, uint32_t big, uint64
     if (tid == 0) PMH_STAT(sm, kStRepairs, 1);  // more rounds over the whole set, above Tmin
     set_rounds<V, NW>(A, R, Tmin * A.grow, Tmin, K, keys, q, fy, sm);
   }
-  epilogue<NW>(A, R, set, keys, sm);
+  epilogue<NW, kBbit>(A, R, set, keys, sm);
 }
 
 // Dynamic LDS: log table (256 cells) | keys[m] | chain queue | Fisher-Yates arrays.
@@ -1171,7 +1194,7 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
 // Persistent grid.  Work items: first the chunks of the split sets (heavy
 // first), then one item per remaining set.  meta = {split sets, chunk items,
 // total items}, written by k_order.
-template <int V, int NW>
+template <int V, int NW, bool kBbit = false>
 __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
   __shared__ Shared sm;
   __shared__ uint32_t job[3];
@@ -1204,13 +1227,13 @@ __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
     __syncthreads();
     if (v >= total) break;
     if (v < vbig) process_chunk<V, NW>(A, A.order[j1], j1, j2, keys, q, qcap, fy, lt, sm);
-    else process_set<V, NW>(A, A.order[j1], keys, q, qcap, fy, lt, sm);
+    else process_set<V, NW, kBbit>(A, A.order[j1], keys, q, qcap, fy, lt, sm);
   }
 }
 
 // Persistent grid over the split sets (order[0 .. meta[0])), after the
 // chunk kernel.
-template <int V, int NW>
+template <int V, int NW, bool kBbit = false>
 __global__ __launch_bounds__(NW * 64) void k_big_finish(HashArgs A) {
   __shared__ Shared sm;
   __shared__ uint32_t job;
@@ -1228,7 +1251,7 @@ __global__ __launch_bounds__(NW * 64) void k_big_finish(HashArgs A) {
     const uint32_t b = job;
     __syncthreads();
     if (b >= num_big) break;
-    finish_set<V, NW>(A, A.order[b], b, keys, q, qcap, fy, lt, sm);
+    finish_set<V, NW, kBbit>(A, A.order[b], b, keys, q, qcap, fy, lt, sm);
   }
 }
 
@@ -1791,16 +1814,24 @@ template <int V, int NW>
 static bool shape_ok(const HashArgs& a, size_t lds) {
   return a.qcap >= batch_size(NW) && lds >= lds_bytes_q(V, a.m, NW, a.qcap);
 }
+// Launches with an out_bbit output take the instantiations with the b-bit
+// epilogue.
 template <int V, int NW>
 static hipError_t launch_hash_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
   if (!shape_ok<V, NW>(a, lds)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_hash_persistent<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
+  if (a.out_bbit)
+    hipLaunchKernelGGL((k_hash_persistent<V, NW, true>), dim3(grid), dim3(NW * 64), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_hash_persistent<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
   return hipGetLastError();
 }
 template <int V, int NW>
 static hipError_t launch_finish_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
   if (!shape_ok<V, NW>(a, lds)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_big_finish<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
+  if (a.out_bbit)
+    hipLaunchKernelGGL((k_big_finish<V, NW, true>), dim3(grid), dim3(NW * 64), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_big_finish<V, NW>), dim3(grid), dim3(NW * 64), lds, s, a);
   return hipGetLastError();
 }
 template <int V, int NW>

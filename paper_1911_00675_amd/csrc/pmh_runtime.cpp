@@ -383,6 +383,28 @@ int pmh_hash_sets_noalloc(pmh_ctx* c, const uint64_t* ids, const double* w, cons
   return enqueue_batched(c, a, &wb, (hipStream_t)stream, 0, 0, ev0, ev1);
 }
 
+int pmh_hash_sets_bbit(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
+                       uint32_t b, uint64_t* out_bbit, uint32_t* idx, double* val, uint64_t* id, uint64_t* keys,
+                       void* stream) {
+  int rc = check_hash_args(c, ids, w, off, num_sets);
+  if (rc || num_sets == 0) return rc;
+  if (!out_bbit || !(b == 1 || b == 2 || b == 4 || b == 8 || b == 16)) return PMH_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  rc = ensure_work(c, &c->work, num_sets);
+  if (rc) return rc;
+  HashArgs a = make_args(c, ids, w, off, num_sets, idx, val, id, keys, &c->work);
+  a.out_bbit = out_bbit;
+  a.bbit_b = b;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (c->tnext < c->tcount) {
+    ev0 = c->tev[2 * c->tnext];
+    ev1 = c->tev[2 * c->tnext + 1];
+    c->tnext++;
+  }
+  return enqueue_batched(c, a, &c->work, (hipStream_t)stream, 0, 0, ev0, ev1);
+}
+
 int pmh_hash_sets_binary(pmh_ctx* c, const uint64_t* ids, const uint64_t* off, uint64_t num_sets, uint32_t* idx,
                          double* val, uint64_t* id, uint64_t* keys, void* stream) {
   if (!c) return PMH_ERR_ARG;

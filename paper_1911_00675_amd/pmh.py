@@ -42,6 +42,7 @@ SIGNATURES = {
     "pmh_bbit_allpairs": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp]),
     "pmh_hash_sets_plain": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_hash_sets_noalloc": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
+    "pmh_hash_sets_bbit": (_i32, [_vp] * 4 + [_u64, _u32] + [_vp] * 6),
     "pmh_hash_sets_graph": (_i32, [_vp] * 4 + [_u64] + [_vp] * 5),
     "pmh_get_status": (_i32, [_vp, _vp]),
     "pmh_timing_begin": (_i32, [_vp, _i32]),
@@ -170,6 +171,7 @@ class Signatures:
     val: object = None   # float64 [S, m]
     id: object = None    # int64 [S, m], bit pattern of uint64
     keys: object = None  # int64 [S, m], bit pattern of uint64
+    bbit: object = None  # int64 [S, ceil(m b / 64)]: b-bit reduction (hash_sets(..., bbit=b))
 
 
 @dataclass
@@ -211,7 +213,7 @@ class Context:
             keys=torch.empty(shape, dtype=torch.int64, device="cuda") if "keys" in outputs else None)
 
     def hash_sets(self, ids, weights, offsets, out: Signatures | None = None, mode: str = "batched",
-                  stream=None, outputs=("idx", "val", "id", "keys")) -> Signatures:
+                  stream=None, outputs=("idx", "val", "id", "keys"), bbit: int = 0) -> Signatures:
         """Signatures of a CSR batch of device tensors (ids int64/uint64,
         weights float64, offsets int64/uint64 with num_sets+1 entries).
         mode: "batched", "plain", "graph", "noalloc" (ProbMinHash of the
@@ -224,6 +226,21 @@ class Context:
         if out is None:
             out = self.alloc_outputs(num_sets, outputs)
         i64 = (torch.int64, torch.uint64)
+        if bbit:
+            if mode != "batched":
+                raise ValueError("the fused b-bit reduction runs in the batched form")
+            words = (self.m * bbit + 63) // 64
+            if out.bbit is None:
+                out.bbit = torch.empty((num_sets, words), dtype=torch.int64, device="cuda")
+            elif out.bbit.numel() != num_sets * words:
+                raise ValueError(f"out.bbit holds {out.bbit.numel()} entries, expected {num_sets} x {words}")
+            rc = lib().pmh_hash_sets_bbit(
+                self._c, _dptr(ids, i64, "ids"), _dptr(weights, (torch.float64,), "weights"),
+                _dptr(offsets, i64, "offsets"), num_sets, int(bbit), _dptr(out.bbit, (torch.int64,), "bbit"),
+                _dptr(out.idx, (torch.int32,), "idx"), _dptr(out.val, (torch.float64,), "val"),
+                _dptr(out.id, i64, "id"), _dptr(out.keys, i64, "keys"), _stream_ptr(stream))
+            _check(rc, "pmh_hash_sets_bbit")
+            return out
         if mode == "binary":
             if weights is not None:
                 raise ValueError("binary mode takes no weights")

@@ -77,3 +77,35 @@ def test_corrected_estimate_on_device_signatures(pmh):
         est = O.bbit_estimate(c, m, b)
         assert abs(est - J) < 6 * np.sqrt(pr * (1 - pr) / m) / (1 - r)
     ctx.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_fused_epilogue_bit_exact(pmh, variant):
+    """The b-bit words written by the hash kernel's epilogue
+    (pmh_hash_sets_bbit) equal the oracle's packing of the oracle's
+    signature ids for every b, on ragged batches with empty and split sets,
+    with the other outputs present (sets split) or absent (no merge row, no
+    split), and the separate pack kernel's words."""
+    from paper_1911_00675_amd import workloads as W
+    rng = np.random.default_rng(900 + variant)
+    sizes = [0, 1, 3, 80, 40000, 0, 700, 5]
+    n = sum(sizes)
+    b_ = W.Batch(rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64), rng.exponential(size=n) + 1e-3,
+                 np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64))
+    d = [pmh.to_device(a) for a in (b_.ids, b_.weights, b_.offsets)]
+    for m in (2, 63, 1000, 4096):
+        print(f"fused bbit PMH{variant} m={m}", flush=True)
+        want_keys = O.sign_batch(variant, SEED, m, b_.ids, b_.weights, b_.offsets, nthreads=8)
+        ids = np.stack([O.decode(want_keys[s], b_.set(s)[0])[2] for s in range(b_.num_sets)])
+        ctx = pmh.Context(SEED, m, variant)
+        for bb in (1, 2, 4, 8, 16):
+            want = O.bbit_pack(ids, m, bb)
+            for outputs in (("idx", "val", "id", "keys"), ()):
+                sig = ctx.hash_sets(*d, outputs=outputs, bbit=bb)
+                assert ctx.status() == pmh.PMH_OK
+                assert np.array_equal(sig.bbit.cpu().numpy().view(np.uint64), want), (m, bb, outputs)
+                if outputs:
+                    assert np.array_equal(sig.keys.cpu().numpy().view(np.uint64), want_keys)
+                    sep = pmh.bbit_pack(sig.id, bb).cpu().numpy().view(np.uint64)
+                    assert np.array_equal(sep, want)
+        ctx.close()
