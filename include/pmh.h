@@ -70,7 +70,8 @@ enum {
   PMH_ERR_OOM = 7,            /* device or host allocation failed */
   PMH_ERR_BUSY = 8,           /* serving queue full */
   PMH_ERR_NOT_READY = 9,      /* serving request still in flight */
-  PMH_ERR_SCRATCH_LIMIT = 10  /* pmh_hash_sets_noalloc: more sets than its static work buffer holds */
+  PMH_ERR_SCRATCH_LIMIT = 10, /* pmh_hash_sets_noalloc: more sets than its static work buffer holds */
+  PMH_ERR_NO_ENTRY = 11       /* pmh_tuning_load: no stored tuning for this device, m and variant */
 };
 
 /* Tunables of the per-set schedule.  None of them changes any result. */
@@ -248,6 +249,15 @@ int pmh_set_caps(pmh_ctx* ctx, uint32_t imax, uint32_t te_rounds, uint32_t redra
  * *best (host, may be NULL) receives it.  Synchronous. */
 int pmh_autotune(pmh_ctx* ctx, const uint64_t* ids, const double* weights, const uint64_t* offsets,
                  uint64_t num_sets, int trials, void* stream, pmh_tuning* best);
+
+/* Stored tunings (text file at [host] path, one line per key): the key is the
+ * context's device architecture (gcnArchName) and compute-unit count, m and
+ * variant.  pmh_tuning_save writes the context's current tuning under its key
+ * (replacing an older line; the file is rewritten through a temporary file
+ * and renamed).  pmh_tuning_load applies the stored tuning for the context's
+ * key (validated as pmh_set_tuning does), or returns PMH_ERR_NO_ENTRY. */
+int pmh_tuning_save(const pmh_ctx* ctx, const char* path);
+int pmh_tuning_load(pmh_ctx* ctx, const char* path);
 
 /* Estimator of eq. (3) for one pair of signatures of size m, [host] inputs:
  * fraction of components k with idA[k] == idB[k], empty components (idx

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "../../include/pmh.h"
@@ -43,6 +47,66 @@ double measure(pmh_ctx* c, const HashArgs& base, int trials, hipStream_t s, hipE
 }
 
 }  // namespace
+
+// Key of a stored tuning: the device architecture and compute-unit count,
+// m and the variant (the schedule's best knobs depend on all four).
+static int tuning_key(const pmh_ctx* c, std::string* key) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, c->device) != hipSuccess) return PMH_ERR_DEVICE;
+  std::ostringstream os;
+  os << p.gcnArchName << ' ' << p.multiProcessorCount << ' ' << c->m << ' ' << c->variant;
+  *key = os.str();
+  return PMH_OK;
+}
+
+// Tunings are stored one per line: "<arch> <CUs> <m> <variant>" and the 11
+// knobs in pmh_tuning order.
+extern "C" int pmh_tuning_save(const pmh_ctx* c, const char* path) {
+  if (!c || !path) return PMH_ERR_ARG;
+  std::string key;
+  int rc = tuning_key(c, &key);
+  if (rc) return rc;
+  std::vector<std::string> keep;
+  {
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line))
+      if (!line.empty() && line.compare(0, key.size() + 1, key + " ") != 0) keep.push_back(line);
+  }
+  char buf[512];
+  const Tuning& t = c->tune;
+  snprintf(buf, sizeof buf, "%s %.17g %.17g %d %.17g %d %d %d %d %.17g %d %.17g", key.c_str(), t.c0, t.grow,
+           t.max_rounds, t.chain_expect, t.lane_budget, t.waves, t.kmax_refresh, t.blocks_per_cu, t.mini_expect,
+           t.split_log2, t.c0_split);
+  keep.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return PMH_ERR_ARG;
+    for (const std::string& l : keep) out << l << '\n';
+    if (!out) return PMH_ERR_ARG;
+  }
+  return std::rename(tmp.c_str(), path) == 0 ? PMH_OK : PMH_ERR_ARG;
+}
+
+extern "C" int pmh_tuning_load(pmh_ctx* c, const char* path) {
+  if (!c || !path) return PMH_ERR_ARG;
+  std::string key;
+  int rc = tuning_key(c, &key);
+  if (rc) return rc;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
+    std::istringstream is(line.substr(key.size() + 1));
+    pmh_tuning t;
+    if (!(is >> t.c0 >> t.grow >> t.max_rounds >> t.chain_expect >> t.lane_budget >> t.waves >> t.kmax_refresh >>
+          t.blocks_per_cu >> t.mini_expect >> t.split_log2 >> t.c0_split))
+      return PMH_ERR_ARG;
+    return pmh_set_tuning(c, &t);
+  }
+  return PMH_ERR_NO_ENTRY;
+}
 
 extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, const uint64_t* off, uint64_t num_sets,
                             int trials, void* stream, pmh_tuning* best_out) {

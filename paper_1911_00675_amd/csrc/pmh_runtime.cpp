@@ -193,6 +193,7 @@ const char* pmh_status_str(int st) {
     case PMH_ERR_BUSY: return "serving queue full";
     case PMH_ERR_NOT_READY: return "request not finished";
     case PMH_ERR_SCRATCH_LIMIT: return "batch exceeds the no-allocation work buffer (at most 2^20 sets)";
+    case PMH_ERR_NO_ENTRY: return "no stored tuning for this device, m and variant";
     default: return "unknown status";
   }
 }

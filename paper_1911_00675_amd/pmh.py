@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpmh_stats.so" if os.environ.get("PMH_LIB") ==
 
 PMH_OK, PMH_ERR_ARG, PMH_ERR_M_RANGE, PMH_ERR_VARIANT_M, PMH_ERR_WEIGHT = 0, 1, 2, 3, 4
 PMH_ERR_SET_TOO_LARGE, PMH_ERR_DEVICE, PMH_ERR_OOM, PMH_ERR_BUSY, PMH_ERR_NOT_READY = 5, 6, 7, 8, 9
-PMH_ERR_SCRATCH_LIMIT = 10
+PMH_ERR_SCRATCH_LIMIT, PMH_ERR_NO_ENTRY = 10, 11
 IDX_EMPTY = 0xFFFFFFFF
 KEY_EMPTY = 0xFFFFFFFFFFFFFFFF
 
@@ -51,6 +51,8 @@ SIGNATURES = {
     "pmh_set_caps": (_i32, [_vp, _u32, _u32, _u32, _u32]),
     "pmh_get_tuning": (_i32, [_vp, _vp]),
     "pmh_autotune": (_i32, [_vp] * 4 + [_u64, _i32, _vp, _vp]),
+    "pmh_tuning_save": (_i32, [_vp, ctypes.c_char_p]),
+    "pmh_tuning_load": (_i32, [_vp, ctypes.c_char_p]),
     "pmh_estimate": (_i32, [_vp, _vp, _vp, _vp, _u32, _vp]),
     "pmh_estimate_pairs": (_i32, [_vp, _vp, _vp, _vp, _u32, _u64, _vp, _vp]),
     "pmh_allpairs_counts": (_i32, [_vp, _u32, _u32, _vp, _vp]),
@@ -320,7 +322,24 @@ class Context:
         _check(lib().pmh_set_caps(self._c, int(imax), int(te_rounds), int(redraws), int(lemire_floor)),
                "pmh_set_caps")
 
-    def autotune(self, ids, weights, offsets, trials: int = 3, stream=None) -> dict:
+    def save_tuning(self, path: str):
+        """Store the current tuning under (device arch, CUs, m, variant)."""
+        _check(lib().pmh_tuning_save(self._c, os.fsencode(path)), "pmh_tuning_save")
+
+    def load_tuning(self, path: str) -> bool:
+        """Apply the stored tuning for this context's key; False if none."""
+        rc = lib().pmh_tuning_load(self._c, os.fsencode(path))
+        if rc == PMH_ERR_NO_ENTRY:
+            return False
+        _check(rc, "pmh_tuning_load")
+        return True
+
+    def autotune(self, ids, weights, offsets, trials: int = 3, stream=None, cache: str | None = None) -> dict:
+        """Time candidate schedules on this batch and keep the fastest.  With
+        a cache file, a stored tuning for this device, m and variant is used
+        instead, and a new result is stored there."""
+        if cache and self.load_tuning(cache):
+            return self.get_tuning().as_dict()
         torch = _torch()
         i64 = (torch.int64, torch.uint64)
         best = pmh_tuning()
@@ -328,6 +347,8 @@ class Context:
                                 _dptr(offsets, i64, "offsets"), int(offsets.numel()) - 1, trials,
                                 _stream_ptr(stream), ctypes.byref(best))
         _check(rc, "pmh_autotune")
+        if cache:
+            self.save_tuning(cache)
         return best.as_dict()
 
     # --------------------------------------------------------------- validation

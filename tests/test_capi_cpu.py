@@ -43,7 +43,7 @@ def test_binding_covers_every_symbol():
 
 
 def test_status_strings(lib):
-    for code in range(0, 11):
+    for code in range(0, 12):
         assert lib.pmh_status_str(code)
     assert lib.pmh_status_str(999) == b"unknown status"
 
