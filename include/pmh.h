@@ -81,7 +81,8 @@ typedef struct {
   int max_rounds;     /* rounds before the unbounded final round (>= 1) */
   double chain_expect;/* elements expecting more points go to wave-chain mode */
   int lane_budget;    /* lane-mode points before an element moves to chain mode */
-  int waves;          /* wavefronts per workgroup: 1, 2 or 4 (default 2; 4 for m > 1536) */
+  int waves;          /* wavefronts per workgroup: 1, 2, 4, or 8 for ProbMinHash2/4 (default 2;
+                         4 for m > 1536; fewer where the LDS does not fit) */
   int kmax_refresh;   /* element batches between stop-limit refreshes (>= 1) */
   int blocks_per_cu;  /* persistent grid = CUs * this (0: occupancy limit) */
   double mini_expect; /* ProbMinHash1/3 elements expecting more points run as 4-lane mini-chains */

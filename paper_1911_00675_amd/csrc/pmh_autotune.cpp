@@ -139,8 +139,9 @@ extern "C" int pmh_autotune(pmh_ctx* c, const uint64_t* ids, const double* w, co
       };
       switch (knob) {
         case 0:
-          for (int wv : {1, 2, 4})
-            if (lds_bytes(c->variant, c->m, wv) <= c->lds_limit) add([&](Tuning& t) { t.waves = wv; });
+          for (int wv : {1, 2, 4, 8})
+            if (wv <= max_waves(c->variant) && lds_bytes(c->variant, c->m, wv) <= c->lds_limit)
+              add([&](Tuning& t) { t.waves = wv; });
           break;
         case 1:
           for (double c0 : {1.0, 2.0, 3.0, 4.0, 6.0})

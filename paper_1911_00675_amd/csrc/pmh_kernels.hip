@@ -50,9 +50,9 @@ constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
 // ProbMinHash4 25.0 -> 14.0 ms with 16 steps; the skewed batch (m = 4096,
 // four waves) went 14.1 -> 15.1 ms with 16 and keeps 4.
 template <int V, int NW>
-constexpr uint32_t kFyLaneSteps = V == 4 && NW == 4 ? 4 : 16;
+constexpr uint32_t kFyLaneSteps = V == 4 && NW >= 4 ? 4 : 16;
 template <int V, int NW>
-constexpr bool kFyLaneRolled = V == 4 && NW != 4;
+constexpr bool kFyLaneRolled = V == 4 && NW < 4;
 constexpr uint32_t kEpt = 2;                     // elements per thread per batch
 // Per-wave tables that resolve the dependencies of a chain-mode tile of 64
 // Fisher-Yates steps (ProbMinHash2/4): win[r] = 1 + the latest step of the
@@ -62,9 +62,10 @@ constexpr int kFyBuckets = 128;
 // Waves of a workgroup that run ProbMinHash2/4 chain elements, each with its
 // own label array u16[m] and tables; the others skip the chain pass.  At
 // m = 4096 four arrays took a four-wave workgroup to 81 KB of LDS (one per
-// CU); two leave room for two.
-constexpr int kFyWaves = 2;
-__host__ __device__ constexpr int fy_waves(int nw) { return nw < kFyWaves ? nw : kFyWaves; }
+// CU); two leave room for two.  Eight-wave workgroups (ProbMinHash2/4 only)
+// give every wave an array: one workgroup of 126 KB per CU at m = 4096, with
+// twice the chain waves of two four-wave workgroups.
+__host__ __device__ constexpr int fy_waves(int nw) { return nw == 8 ? 8 : nw < 2 ? nw : 2; }
 struct FyScratch {
   uint64_t bkt[kFyBuckets];
   uint32_t win[64];
@@ -1859,6 +1860,8 @@ static hipError_t occ_t(size_t lds, int* out) {
     case 64 + 1: return FN<4, 1>(__VA_ARGS__);                      \
     case 64 + 2: return FN<4, 2>(__VA_ARGS__);                      \
     case 64 + 4: return FN<4, 4>(__VA_ARGS__);                      \
+    case 32 + 8: return FN<2, 8>(__VA_ARGS__);                      \
+    case 64 + 8: return FN<4, 8>(__VA_ARGS__);                      \
     default: return hipErrorInvalidValue;                           \
   }
 

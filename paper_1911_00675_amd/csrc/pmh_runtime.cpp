@@ -44,20 +44,24 @@ size_t lds_limit_bytes(int device) {
   return p.sharedMemPerBlock - lds_static_bytes();  // budget for the dynamic part
 }
 
+int max_waves(int variant) { return (variant == 2 || variant == 4) ? 8 : 4; }
+
 int effective_waves(const pmh_ctx* c) {
   int w = c->tune.waves;
-  if (w != 1 && w != 2 && w != 4) w = 4;
+  if (w != 1 && w != 2 && w != 4 && w != 8) w = 4;
+  if (w > max_waves(c->variant)) w = max_waves(c->variant);
   while (w > 1 && lds_bytes(c->variant, c->m, w) > c->lds_limit) w >>= 1;
   return w;
 }
 
-static int waves_slot(int waves) { return waves == 1 ? 0 : waves == 2 ? 1 : 2; }
+static int waves_slot(int waves) { return waves == 1 ? 0 : waves == 2 ? 1 : waves == 4 ? 2 : 3; }
 
 // The chain queue takes the LDS left over at the register-limited occupancy
 // (the workgroups per CU with a one-batch queue), in steps of 32 entries and
 // up to 8 batches: a bigger queue means fewer mid-round chain passes.
 void plan_queues(pmh_ctx* c) {
-  for (int waves : {1, 2, 4}) {
+  for (int waves : {1, 2, 4, 8}) {
+    if (waves > max_waves(c->variant)) continue;
     const uint32_t batch = batch_size(waves);
     uint32_t best = 2 * batch;
     int occ0 = 0;
@@ -233,6 +237,15 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   // 3 or more (skewed batch at m = 4096: ProbMinHash1 17.8 -> 9.7 ms,
   // ProbMinHash3 16.3 -> 8.8 ms; at m = 1024 two waves stay ahead).
   if (m > 1536) c->tune.waves = 4;
+  // ProbMinHash2/4: only the chain-capable waves (those with a label array)
+  // share chain elements, so four-wave workgroups (two such waves) were never
+  // the fastest; two waves up to m = 2048, eight (all with arrays) at m = 4096:
+  // skewed batch at m = 4096 13.9 -> 11.5 ms (ProbMinHash2), 14.3 -> 10.8 ms
+  // (ProbMinHash4) against four waves; mixed batch at m = 2048 two waves
+  // 26 / 34 ms against 44 / 98 ms with four.
+  // Where eight do not fit (m = 8192) four waves keep one wave per SIMD in the
+  // single workgroup a CU holds.
+  if (variant == 2 || variant == 4) c->tune.waves = m <= 3072 ? 2 : lds_bytes(variant, m, 8) <= lim ? 8 : 4;
   c->device = dev;
   c->lds_limit = lim;
   hipDeviceProp_t prop;
@@ -543,7 +556,8 @@ int pmh_get_status(pmh_ctx* c, void* stream) {
 int pmh_set_tuning(pmh_ctx* c, const pmh_tuning* t) {
   if (!c || !t) return PMH_ERR_ARG;
   if (!(t->grow > 1.0) || t->max_rounds < 1 || t->lane_budget < 1 || t->kmax_refresh < 1 ||
-      (t->waves != 1 && t->waves != 2 && t->waves != 4) || t->blocks_per_cu < 0 || !(t->c0 > -100.0) ||
+      (t->waves != 1 && t->waves != 2 && t->waves != 4 && t->waves != 8) || t->blocks_per_cu < 0 ||
+      !(t->c0 > -100.0) ||
       !(t->chain_expect >= 0.0) || !(t->mini_expect >= 0.0) || t->split_log2 < 0 || t->split_log2 == 1 ||
       t->split_log2 > 21 || !(t->c0_split > -100.0) || !(t->c0_split < 1e6))
     return PMH_ERR_ARG;

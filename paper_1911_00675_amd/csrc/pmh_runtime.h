@@ -61,7 +61,7 @@ struct pmh_ctx {
   int device = 0;
   int num_cu = 1;
   size_t lds_limit = 65536;
-  uint32_t qcap[3] = {128, 256, 512};  // chain queue entries for 1, 2, 4 waves per workgroup
+  uint32_t qcap[4] = {256, 512, 1024, 2048};  // chain queue entries for 1, 2, 4, 8 waves per workgroup
   void* table_mem = nullptr;
   pmh::Tables t{};
   uint32_t* status = nullptr;
@@ -83,6 +83,7 @@ struct pmh_ctx {
 };
 
 namespace pmh {
+int max_waves(int variant);  // 8 for ProbMinHash2/4, 4 for ProbMinHash1/3
 int effective_waves(const pmh_ctx* c);
 // Dynamic LDS of a hash launch with `waves` per workgroup; *qcap receives the
 // chain queue capacity to pass in HashArgs.

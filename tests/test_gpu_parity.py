@@ -232,6 +232,7 @@ def test_schedule_invariance(pmh, variant):
                dict(lane_budget=1, waves=1),
                dict(blocks_per_cu=1), dict(kmax_refresh=1), dict(c0=20.0), dict(waves=4),
                dict(waves=4, chain_expect=0.0),
+               dict(waves=8), dict(waves=8, chain_expect=0.0),
                dict(kmax_refresh=3, max_rounds=1),
                # many thin rounds (ProbMinHash3 resumes each element near the
                # previous threshold) in every mode
@@ -298,7 +299,8 @@ def test_split_sets(pmh, variant, m):
 
 @pytest.mark.parametrize("variant", [1, 2, 3, 4])
 def test_large_m_four_waves(pmh, variant):
-    """m = 4096, where contexts default to 4 waves per workgroup: ragged sets
+    """m = 4096, where contexts default to 4 waves per workgroup (8 for
+    ProbMinHash2/4): ragged sets
     up to 40,000 elements (split ones included) in the batched and graph
     forms, and the same keys with 1 and 2 waves."""
     print(f"m=4096 PMH{variant}", flush=True)
@@ -311,8 +313,8 @@ def test_large_m_four_waves(pmh, variant):
     b = W.Batch(ids, w, off)
     want = O.sign_batch(variant, SEED, m, ids, w, off, nthreads=8)
     ctx = pmh.Context(SEED, m, variant)
-    assert ctx.get_tuning().waves == 4
-    for cfg in (dict(), dict(split_log2=12), dict(waves=2), dict(waves=1)):
+    assert ctx.get_tuning().waves == (4 if variant in (1, 3) else 8)
+    for cfg in (dict(), dict(split_log2=12), dict(waves=2), dict(waves=1), dict(waves=8)):
         ctx.set_tuning(**cfg)
         for mode in ("batched", "graph"):
             sig, st = _keys(ctx, b, mode)
