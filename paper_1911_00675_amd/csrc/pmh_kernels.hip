@@ -70,6 +70,15 @@ struct FyScratch {
   uint64_t bkt[kFyBuckets];
   uint32_t win[64];
 };
+// ProbMinHash4 lane-mode elements are sorted per batch by expected points
+// (kSortClasses classes, longest first) so the 64 lanes of a wave get streams
+// of similar length: a wave runs as many steps as its longest stream.  LDS
+// after the label arrays: counts[16], offsets[16], then one u16 batch index
+// per element.
+constexpr int kSortClasses = 16;
+__host__ __device__ constexpr size_t sort_region_offset(int nf, uint32_t m) {
+  return ((size_t)nf * (sizeof(FyScratch) + (size_t)m * 2) + 15) & ~(size_t)15;
+}
 
 // Optional event counters (statistics build only, -DPMH_STATS): accumulated in
 // LDS per workgroup and added to HashArgs::points[0..15] when a set ends.
@@ -903,6 +912,94 @@ __device__ double block_weight_sum(const HashArgs& A, const Round& R, uint32_t p
   return W;
 }
 
+// ProbMinHash4 lane mode over one batch: streams expecting more than
+// chain_expect points go to the chain queue, the others run one per lane.  In
+// sets whose elements expect more than a point each (R.sort) they are first
+// counted into classes by expected points and dealt to the lanes longest
+// first through LDS (weights and ids then read again, from cache), so the 64
+// lanes of a wave get streams of similar length: a wave runs as many steps as
+// its longest stream.  Otherwise each thread keeps its own prefetched ones.
+// (`sort` is block-uniform.)
+template <int V, int NW>
+__device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, uint32_t base, uint32_t p1,
+                                           const double* wc, const uint64_t* idc, double Teff, uint64_t kmax,
+                                           uint64_t* keys, ChainEntry* q, uint16_t* fy, Shared& sm, bool sort) {
+  constexpr int BS = NW * 64;
+  const int tid = threadIdx.x;
+  uint32_t pk[kEpt];
+  double wk[kEpt];
+  uint64_t idk[kEpt];
+  int cls[kEpt];
+#pragma unroll
+  for (uint32_t k = 0; k < kEpt; ++k) {
+    cls[k] = -1;
+    pk[k] = base + k * BS + tid;
+    wk[k] = wc[k];
+    idk[k] = idc[k];
+    if (pk[k] >= p1) continue;
+    const double w = wc[k];
+    if (!weight_ok(w)) continue;
+    PMH_STAT(sm, kStElems, 1);
+    const double lam = w * Teff;  // expected points generated
+    if (lam > A.chain_expect) {
+      push_long(sm, q, pk[k], 1, 0);
+      continue;
+    }
+    cls[k] = lam < (double)(kSortClasses - 1) ? (int)lam : kSortClasses - 1;
+  }
+  if (sort) {  // block-uniform
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(fy) +
+                                                sort_region_offset(fy_waves(NW), R.m));
+    uint32_t* off = cnt + kSortClasses;
+    uint16_t* idx = reinterpret_cast<uint16_t*>(off + kSortClasses);
+    uint32_t pos[kEpt];
+#pragma unroll
+    for (uint32_t k = 0; k < kEpt; ++k) pos[k] = cls[k] >= 0 ? atomicAdd(&cnt[cls[k]], 1u) : 0u;
+    __syncthreads();
+    if (tid < 64) {  // offsets, longest class first
+      const uint32_t c = tid < kSortClasses ? cnt[kSortClasses - 1 - tid] : 0u;
+      const uint32_t incl = wave_incl_scan_u32(c);
+      if (tid < kSortClasses) off[kSortClasses - 1 - tid] = incl - c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kEpt; ++k)
+      if (cls[k] >= 0) idx[off[cls[k]] + pos[k]] = (uint16_t)(k * BS + tid);
+    const uint32_t total = off[0] + cnt[0];  // class 0 comes last
+    // one class only (equal weights): nothing to reorder (every wave reads
+    // the same counts, so this is block-uniform)
+    const int lane = tid & 63;
+    const bool one = __builtin_popcountll(__ballot(lane < kSortClasses && cnt[lane & (kSortClasses - 1)] != 0u)) <= 1;
+    __syncthreads();
+    if (tid < kSortClasses) cnt[tid] = 0u;  // read above; the next batch counts after two more barriers
+    if (!one) {
+#pragma unroll
+      for (uint32_t k = 0; k < kEpt; ++k) {
+        const uint32_t s = k * BS + tid;
+        cls[k] = s < total ? 0 : -1;
+        if (s < total) {
+          pk[k] = base + idx[s];
+          wk[k] = elem_w(R, pk[k]);
+          idk[k] = R.ids[pk[k]];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kEpt; ++k) {
+    if (cls[k] < 0) continue;
+    const int steps = lane_elem<V, NW>(A, R, pk[k], 1.0 / wk[k], mix64(idk[k] ^ R.K0), kmax, keys, sm, q,
+                                       A.lane_budget, 1);
+#ifdef PMH_STATS
+    int mx = steps;
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+    if ((threadIdx.x & 63) == __builtin_ctzll(__ballot(true))) PMH_STAT(sm, kStLaneIters, mx);
+#else
+    (void)steps;
+#endif
+  }
+}
+
 // One round over elements [p0, p1): every point below R.T is generated and
 // the ones that can still lower a key are applied (stop limit kmax_start at
 // entry, refreshed as keys fall).  Returns the block max of the keys.
@@ -920,6 +1017,11 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
   }
   __syncthreads();
   const uint32_t batch = kEpt * BS;
+  // ProbMinHash2/4: ordering lane-mode streams pays where an element expects
+  // more than one point on average (T0 W = m (ln m + c0) points over n
+  // elements); sets of mostly one-point elements keep the prefetched order.
+  bool sort = false;
+  if constexpr (V == 4) sort = (double)R.n < (double)m * (log((double)m) + A.c0);
   // The weights and ids of the next batch are loaded while this one runs
   // (not for ProbMinHash3, where the extra registers cost a workgroup per CU
   // at m = 1024 and the loads are better issued on demand).
@@ -957,6 +1059,9 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
     // count of an element is its weight times the smaller of T and that value
     const double Tk = kmax == kEmptyKey ? R.T : __longlong_as_double((long long)(kmax & ~kPosMask));
     const double Teff = Tk < R.T ? Tk : R.T;
+    if constexpr (V == 4) {
+      lane_batch<V, NW>(A, R, base, p1, wc, idc, Teff, kmax, keys, q, fy, sm, sort);
+    } else {
 #pragma unroll
     for (uint32_t k = 0; k < kEpt; ++k) {
       const uint32_t p = base + k * BS + tid;
@@ -986,6 +1091,7 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
 #else
       (void)steps;
 #endif
+    }
     }
     PMH_TOC(sm, kStCycBatch, t_batch);
     PMH_TIC(t_bar);
@@ -1188,6 +1294,8 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
   if constexpr (V == 2 || V == 4) {
     uint64_t* z = reinterpret_cast<uint64_t*>(fy);
     for (uint32_t k = threadIdx.x; k < fy_waves(NW) * sizeof(FyScratch) / 8; k += NW * 64) z[k] = 0ull;
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(fy) + sort_region_offset(fy_waves(NW), m));
+    if (threadIdx.x < kSortClasses) cnt[threadIdx.x] = 0u;
   }
   __syncthreads();
 }
@@ -1798,7 +1906,8 @@ uint32_t batch_size(int waves) { return kEpt * (uint32_t)waves * 64; }
 
 size_t lds_bytes_q(int variant, uint32_t m, int waves, uint32_t qcap) {
   size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry);
-  if (variant == 2 || variant == 4) b += (size_t)fy_waves(waves) * (sizeof(FyScratch) + (size_t)m * 2);
+  if (variant == 2 || variant == 4)
+    b += sort_region_offset(fy_waves(waves), m) + 2 * kSortClasses * 4 + (size_t)batch_size(waves) * 2;
   return b;
 }
 
