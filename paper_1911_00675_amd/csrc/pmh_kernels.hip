@@ -79,6 +79,17 @@ constexpr int kSortClasses = 16;
 __host__ __device__ constexpr size_t sort_region_offset(int nf, uint32_t m) {
   return ((size_t)nf * (sizeof(FyScratch) + (size_t)m * 2) + 15) & ~(size_t)15;
 }
+// Lane mode reads the per-index tables at indices 0..16 only (at most 16
+// register Fisher-Yates steps): a copy of that slice sits in LDS after the
+// sort region, kLaneTab entries per table (ProbMinHash2: beta; ProbMinHash4:
+// gamma, gamma differences, lambda, a, c1), so a step reads LDS instead of
+// waiting on global loads.
+constexpr uint32_t kLaneTab = 17;
+constexpr uint32_t kLogCells = 256;  // stream-logarithm cells at the start of the dynamic LDS
+constexpr uint32_t kLaneTabs = 5;
+__host__ __device__ constexpr size_t lane_tab_offset(int nf, uint32_t m, uint32_t batch) {
+  return (sort_region_offset(nf, m) + 2 * kSortClasses * 4 + (size_t)batch * 2 + 15) & ~(size_t)15;
+}
 
 // Optional event counters (statistics build only, -DPMH_STATS): accumulated in
 // LDS per workgroup and added to HashArgs::points[0..15] when a set ends.
@@ -526,7 +537,12 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
     // slot tr[s] & 0xFFFF; m <= 2^14); longer streams restart in chain mode,
     // whose 64-step tiles cost far more per point for short streams.
     constexpr uint32_t kSteps = kFyLaneSteps<V, NW>;
+    static_assert(kSteps < kLaneTab, "lane-mode table slice too short");
     constexpr int kUnroll = kFyLaneRolled<V, NW> ? 1 : (int)kSteps;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const double* L = reinterpret_cast<const double*>(dyn + kLogCells * sizeof(LogCell) + (size_t)m * 8 +
+                                                      (size_t)R.qcap * sizeof(ChainEntry) +
+                                                      lane_tab_offset(fy_waves(NW), m, kEpt * NW * 64));
     uint32_t tr[kSteps];
     uint64_t tacc = 0;
 #pragma unroll kUnroll
@@ -537,20 +553,23 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       const uint64_t w0 = mix64(pb);
       double x;
       if constexpr (V == 2) {
-        tacc += spacing_fixed(t.beta[i] * exp1(w0, lt));
+        tacc += spacing_fixed(L[i] * exp1(w0, lt));  // beta_i
         x = winv * fixed_value(tacc);
         if (!(x < R.T)) return (int)step + 1;
         if (make_key(x, p) >= kmax) return (int)step + 1;
       } else {
-        const double lb = A.binary ? (double)(i - 1) : winv * t.gam[i - 1];
+        const double gp = L[i - 1];  // gamma_{i-1}
+        const double lb = A.binary ? (double)(i - 1) : winv * gp;
         if (!(lb < R.T)) return (int)step;
         if (make_key(lb, p) >= kmax) return (int)step;
-        if (A.binary)
+        if (A.binary) {
           x = lb + u32v(w0);
-        else if (i < m)
-          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.a[i], t.c1[i], t));
-        else
-          x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
+        } else if (i < m) {
+          x = winv * (gp + L[kLaneTab + i] * trunc_exp(w0, pb, L[2 * kLaneTab + i], L[3 * kLaneTab + i],
+                                                       L[4 * kLaneTab + i], t));
+        } else {
+          x = winv * (gp + t.scal[4] * exp1<false>(w0, lt));
+        }
       }
       PMH_STAT(sm, kStLanePts, 1);
       // Fisher-Yates step i: slot j = (i-1) + U{0..m-i}; label = g[j]; g[j] = g[i-1]
@@ -606,9 +625,25 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
     __builtin_amdgcn_wave_barrier();
   }
   uint64_t pb = pbase(K, i0) + (uint64_t)lane * kPointStep;
+  // ProbMinHash4: the interval tables of a tile's points (gamma_{i-1},
+  // gamma_i - gamma_{i-1}, c1_i) are loaded one tile ahead, so their latency
+  // overlaps the previous tile's Fisher-Yates work (indices clamped to the
+  // tables; the values of points past m are never used).
+  double gp_n = 0.0, dg_n = 0.0, c1_n = 0.0;
+  auto tload = [&](uint32_t ii) {
+    if constexpr (V == 4) {
+      const uint32_t k = ii < m ? ii : m - 1u;
+      gp_n = t.gam[(ii <= m ? ii : m) - 1u];
+      dg_n = t.dgam[k];
+      c1_n = t.c1[k];
+    }
+  };
+  tload(i0 + (uint32_t)lane);
   for (uint32_t tile = 1;; ++tile, pb += 64ull * kPointStep) {
     const uint32_t i = i0 + (uint32_t)lane;
     const bool valid = i <= end;
+    const double gp = gp_n, dg = dg_n, c1v = c1_n;
+    tload(i + 64u);
     const uint64_t w0 = mix64(pb);
     double x = 0.0;
     uint64_t key = kEmptyKey;
@@ -635,16 +670,21 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
     } else {
       stop = !valid;
       if (valid) {
-        const double lb = A.binary ? (double)(i - 1) : winv * t.gam[i - 1];
+        const double lb = A.binary ? (double)(i - 1) : winv * gp;
         stop = !(lb < R.T) || make_key(lb, p) >= kmax;
       }
       if (!stop) {
-        if (A.binary)
+        if (A.binary) {
           x = (double)(i - 1) + u32v(w0);
-        else if (i < m)
-          x = winv * (t.gam[i - 1] + t.dgam[i] * trunc_exp(w0, pb, t.lam[i], t.a[i], t.c1[i], t));
-        else
-          x = winv * (t.gam[m - 1] + t.scal[4] * exp1<false>(w0, lt));
+        } else if (i < m) {
+          // the sampler's fast path needs c1 only; lambda_i and a_i are read
+          // when it falls through
+          double e = c1v * u32v(w0);
+          if (!(e < 1.0)) e = te_slow(pb, t.lam[i], t.a[i], c1v, t.te_rounds, t.expm1c);
+          x = winv * (gp + dg * e);
+        } else {
+          x = winv * (gp + t.scal[4] * exp1<false>(w0, lt));
+        }
         key = make_key(x, p);
       }
     }
@@ -1275,8 +1315,8 @@ __device__ void finish_set(const HashArgs& A, uint64_t set, uint32_t big, uint64
   epilogue<NW, kBbit>(A, R, set, keys, sm);
 }
 
-// Dynamic LDS: log table (256 cells) | keys[m] | chain queue | Fisher-Yates arrays.
-constexpr uint32_t kLogCells = 256;
+// Dynamic LDS: log table (kLogCells cells) | keys[m] | chain queue |
+// Fisher-Yates arrays, sort region and lane-mode tables (ProbMinHash2/4).
 template <int V, int NW>
 __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*& keys, ChainEntry*& q,
                                       uint32_t& qcap, uint16_t*& fy) {
@@ -1296,6 +1336,21 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
     for (uint32_t k = threadIdx.x; k < fy_waves(NW) * sizeof(FyScratch) / 8; k += NW * 64) z[k] = 0ull;
     uint32_t* cnt = reinterpret_cast<uint32_t*>(reinterpret_cast<unsigned char*>(fy) + sort_region_offset(fy_waves(NW), m));
     if (threadIdx.x < kSortClasses) cnt[threadIdx.x] = 0u;
+    double* ltab = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(fy) +
+                                             lane_tab_offset(fy_waves(NW), m, kEpt * NW * 64));
+    const uint32_t ix = threadIdx.x;  // kLaneTab <= 64 threads
+    if (ix < kLaneTab) {
+      if constexpr (V == 2) {
+        ltab[ix] = ix <= m ? A.t.beta[ix] : 0.0;
+      } else {
+        const bool in = ix < m;
+        ltab[ix] = in ? A.t.gam[ix] : 0.0;
+        ltab[kLaneTab + ix] = in ? A.t.dgam[ix] : 0.0;
+        ltab[2 * kLaneTab + ix] = in ? A.t.lam[ix] : 0.0;
+        ltab[3 * kLaneTab + ix] = in ? A.t.a[ix] : 0.0;
+        ltab[4 * kLaneTab + ix] = in ? A.t.c1[ix] : 0.0;
+      }
+    }
   }
   __syncthreads();
 }
@@ -1907,7 +1962,7 @@ uint32_t batch_size(int waves) { return kEpt * (uint32_t)waves * 64; }
 size_t lds_bytes_q(int variant, uint32_t m, int waves, uint32_t qcap) {
   size_t b = kLogCells * sizeof(LogCell) + (size_t)m * 8 + (size_t)qcap * sizeof(ChainEntry);
   if (variant == 2 || variant == 4)
-    b += sort_region_offset(fy_waves(waves), m) + 2 * kSortClasses * 4 + (size_t)batch_size(waves) * 2;
+    b += lane_tab_offset(fy_waves(waves), m, batch_size(waves)) + (size_t)kLaneTabs * kLaneTab * 8;
   return b;
 }
 
