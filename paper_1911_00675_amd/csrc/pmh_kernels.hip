@@ -41,16 +41,17 @@ namespace {
 constexpr double kLn2Hi = 0x1.62e42fefa0000p-1;  // ln 2 rounded to 36 bits
 constexpr double kLn2Lo = 0x1.cf79abc9e3b3ap-40; // ln 2 - kLn2Hi
 // Lane-mode Fisher-Yates steps kept in registers: ProbMinHash2 16 (3 waves
-// per SIMD).  ProbMinHash4 16 in one- and two-wave workgroups, as a rolled
+// per SIMD).  ProbMinHash4 32 in one- and two-wave workgroups, as a rolled
 // loop (the step index is wave-uniform, so the register array is indexed in
-// place: 178 VGPRs, 2 waves per SIMD; unrolled, 8 steps took 185 and 16
-// took 278), but 4 unrolled steps in four-wave workgroups (168 VGPRs), where
-// the m keys in LDS (m > 1536) bound the occupancy anyway and elements need
-// hundreds of points.  Measured: mixed batch with unit weights (m = 1024)
-// ProbMinHash4 25.0 -> 14.0 ms with 16 steps; the skewed batch (m = 4096,
-// four waves) went 14.1 -> 15.1 ms with 16 and keeps 4.
+// place; 2 waves per SIMD either way), but 4 unrolled steps in four-wave
+// workgroups, where the m keys in LDS (m > 1536) bound the occupancy anyway
+// and elements need hundreds of points.  Measured (mixed batch, m = 1024):
+// unit weights ProbMinHash4 25.0 -> 14.0 ms with 16 steps instead of 4; 32
+// steps let streams of up to 32 points stay in lane mode (unit weights 12.5
+// -> 10.5 ms with a chain threshold of 32; the default threshold of 16 is
+// kept for the Pareto-weighted batch, 15.8 -> 15.6 ms).
 template <int V, int NW>
-constexpr uint32_t kFyLaneSteps = V == 4 && NW >= 4 ? 4 : 16;
+constexpr uint32_t kFyLaneSteps = V == 4 && NW >= 4 ? 4 : V == 4 ? 32 : 16;
 template <int V, int NW>
 constexpr bool kFyLaneRolled = V == 4 && NW < 4;
 constexpr uint32_t kEpt = 2;                     // elements per thread per batch
@@ -73,18 +74,18 @@ struct FyScratch {
 // ProbMinHash4 lane-mode elements are sorted per batch by expected points
 // (kSortClasses classes, longest first) so the 64 lanes of a wave get streams
 // of similar length: a wave runs as many steps as its longest stream.  LDS
-// after the label arrays: counts[16], offsets[16], then one u16 batch index
-// per element.
-constexpr int kSortClasses = 16;
+// after the label arrays: counts[kSortClasses], offsets[kSortClasses], then
+// one u16 batch index per element.
+constexpr int kSortClasses = 32;
 __host__ __device__ constexpr size_t sort_region_offset(int nf, uint32_t m) {
   return ((size_t)nf * (sizeof(FyScratch) + (size_t)m * 2) + 15) & ~(size_t)15;
 }
-// Lane mode reads the per-index tables at indices 0..16 only (at most 16
+// Lane mode reads the per-index tables at indices 0..32 only (at most 32
 // register Fisher-Yates steps): a copy of that slice sits in LDS after the
 // sort region, kLaneTab entries per table (ProbMinHash2: beta; ProbMinHash4:
 // gamma, gamma differences, lambda, a, c1), so a step reads LDS instead of
 // waiting on global loads.
-constexpr uint32_t kLaneTab = 17;
+constexpr uint32_t kLaneTab = 33;
 constexpr uint32_t kLogCells = 256;  // stream-logarithm cells at the start of the dynamic LDS
 constexpr uint32_t kLaneTabs = 5;
 __host__ __device__ constexpr size_t lane_tab_offset(int nf, uint32_t m, uint32_t batch) {
