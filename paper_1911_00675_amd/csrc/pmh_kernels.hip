@@ -77,6 +77,12 @@ struct FyScratch {
 // after the label arrays: counts[kSortClasses], offsets[kSortClasses], then
 // one u16 batch index per element.
 constexpr int kSortClasses = 32;
+// Streams expecting more than kLaneSure points (up to chain_expect) stay in
+// lane mode only where an ordered batch holds at least a wave of them;
+// otherwise a few long streams would hold a whole wave, and they go to chain
+// mode instead.
+constexpr int kLaneSure = 16;
+constexpr uint32_t kNoLane = 0xFFFFFFFFu;
 __host__ __device__ constexpr size_t sort_region_offset(int nf, uint32_t m) {
   return ((size_t)nf * (sizeof(FyScratch) + (size_t)m * 2) + 15) & ~(size_t)15;
 }
@@ -982,7 +988,7 @@ __device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, ui
     if (!weight_ok(w)) continue;
     PMH_STAT(sm, kStElems, 1);
     const double lam = w * Teff;  // expected points generated
-    if (lam > A.chain_expect) {
+    if (lam > A.chain_expect || (!sort && lam > (double)kLaneSure)) {
       push_long(sm, q, pk[k], 1, 0);
       continue;
     }
@@ -998,19 +1004,34 @@ __device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, ui
     for (uint32_t k = 0; k < kEpt; ++k) pos[k] = cls[k] >= 0 ? atomicAdd(&cnt[cls[k]], 1u) : 0u;
     __syncthreads();
     if (tid < 64) {  // offsets, longest class first
+      constexpr int kHi = kSortClasses - kLaneSure;  // classes >= kLaneSure come first
       const uint32_t c = tid < kSortClasses ? cnt[kSortClasses - 1 - tid] : 0u;
       const uint32_t incl = wave_incl_scan_u32(c);
-      if (tid < kSortClasses) off[kSortClasses - 1 - tid] = incl - c;
+      const uint32_t hi = (uint32_t)__shfl((int)incl, kHi - 1);
+      if (tid < kSortClasses) {
+        // fewer than a wave of long streams: they go to chain mode
+        const bool drop = hi < 64u && tid < kHi;
+        off[kSortClasses - 1 - tid] = drop ? kNoLane : incl - c - (hi < 64u ? hi : 0u);
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (uint32_t k = 0; k < kEpt; ++k)
-      if (cls[k] >= 0) idx[off[cls[k]] + pos[k]] = (uint16_t)(k * BS + tid);
+    for (uint32_t k = 0; k < kEpt; ++k) {
+      if (cls[k] < 0) continue;
+      const uint32_t o = off[cls[k]];
+      if (o == kNoLane) {
+        push_long(sm, q, base + k * BS + tid, 1, 0);
+        cls[k] = -1;
+      } else {
+        idx[o + pos[k]] = (uint16_t)(k * BS + tid);
+      }
+    }
     const uint32_t total = off[0] + cnt[0];  // class 0 comes last
     // one class only (equal weights): nothing to reorder (every wave reads
     // the same counts, so this is block-uniform)
     const int lane = tid & 63;
-    const bool one = __builtin_popcountll(__ballot(lane < kSortClasses && cnt[lane & (kSortClasses - 1)] != 0u)) <= 1;
+    const bool one = __builtin_popcountll(__ballot(lane < kSortClasses && cnt[lane & (kSortClasses - 1)] != 0u &&
+                                                   off[lane & (kSortClasses - 1)] != kNoLane)) <= 1;
     __syncthreads();
     if (tid < kSortClasses) cnt[tid] = 0u;  // read above; the next batch counts after two more barriers
     if (!one) {

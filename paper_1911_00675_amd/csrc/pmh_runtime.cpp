@@ -246,12 +246,12 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   // Where eight do not fit (m = 8192) four waves keep one wave per SIMD in the
   // single workgroup a CU holds.
   if (variant == 2 || variant == 4) c->tune.waves = m <= 3072 ? 2 : lds_bytes(variant, m, 8) <= lim ? 8 : 4;
-  // ProbMinHash2/4 streams that expect more than 16 points go straight to
-  // chain mode instead of restarting there after their register Fisher-Yates
-  // steps
-  // (mixed batch at m = 1024: ProbMinHash4 18.4 -> 17.2 ms, ProbMinHash2
-  // 13.0 -> 12.5 ms; no change on the skewed batch at m = 4096).
-  if (variant == 2 || variant == 4) c->tune.chain_expect = 16.0;
+  // ProbMinHash2 streams that expect more than 16 points go straight to chain
+  // mode instead of restarting there after their register Fisher-Yates steps
+  // (mixed batch at m = 1024: 13.0 -> 12.5 ms); ProbMinHash4's threshold is
+  // 32, with a per-batch choice above 16 in its ordered lane mode (mixed
+  // batch 15.6 -> 15.3 ms, unit weights 12.2 -> 10.5 ms against 16).
+  if (variant == 2 || variant == 4) c->tune.chain_expect = variant == 4 ? 32.0 : 16.0;
   c->device = dev;
   c->lds_limit = lim;
   hipDeviceProp_t prop;
