@@ -1065,7 +1065,7 @@ __device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, ui
 // One round over elements [p0, p1): every point below R.T is generated and
 // the ones that can still lower a key are applied (stop limit kmax_start at
 // entry, refreshed as keys fall).  Returns the block max of the keys.
-template <int V, int NW>
+template <int V, int NW, bool kPf = false>
 __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, uint32_t p1, uint64_t kmax_start,
                                uint64_t* keys, ChainEntry* q, uint16_t* fy, Shared& sm) {
   constexpr int BS = NW * 64;
@@ -1085,9 +1085,11 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
   bool sort = false;
   if constexpr (V == 4) sort = (double)R.n < (double)m * (log((double)m) + A.c0);
   // The weights and ids of the next batch are loaded while this one runs
-  // (not for ProbMinHash3, where the extra registers cost a workgroup per CU
-  // at m = 1024 and the loads are better issued on demand).
-  constexpr bool kPrefetch = V != 3;
+  // (ProbMinHash3 only in its kPf instantiation: the extra registers, 124 ->
+  // 148 in four-wave workgroups, cost a wave per SIMD wherever the keys in LDS
+  // do not already bound the occupancy, and there the loads are better issued
+  // on demand).
+  constexpr bool kPrefetch = V != 3 || kPf;
   double wn[kEpt];
   uint64_t idn[kEpt];
 #pragma unroll
@@ -1174,14 +1176,14 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
 // Rounds of growing thresholds over the whole set until every key is final
 // (keys must hold the set's current minima on entry, with every point below
 // Tprev applied).
-template <int V, int NW>
+template <int V, int NW, bool kPf = false>
 __device__ void set_rounds(const HashArgs& A, Round& R, double T, double Tprev, uint64_t kmax_round,
                            uint64_t* keys, ChainEntry* q, uint16_t* fy, Shared& sm) {
   for (int round = 0;; ++round) {
     const bool last = round + 1 >= A.max_rounds || !(T < DBL_MAX) || !(T > 0.0);
     R.T = last ? __longlong_as_double(0x7FF0000000000000ll) : T;
     R.Tprev = Tprev;
-    const uint64_t K = round_pass<V, NW>(A, R, 0, R.n, kmax_round, keys, q, fy, sm);
+    const uint64_t K = round_pass<V, NW, kPf>(A, R, 0, R.n, kmax_round, keys, q, fy, sm);
     if (last || K < make_key(R.T, 0)) break;
     Tprev = R.T;
     T = R.T * A.grow;
@@ -1255,7 +1257,7 @@ __device__ void epilogue(const HashArgs& A, const Round& R, uint64_t set, const 
 #endif
 }
 
-template <int V, int NW, bool kBbit = false>
+template <int V, int NW, bool kBbit = false, bool kPf = false>
 __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, ChainEntry* q, uint32_t qcap,
                             uint16_t* fy, const LogCell* lt, Shared& sm) {
   Round R = set_round<NW>(A, set, qcap, lt, sm);
@@ -1278,7 +1280,7 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
     for (uint32_t k = threadIdx.x; k < R.m; k += NW * 64) keys[k] = kEmptyKey;
   }
   const double W = block_weight_sum<NW>(A, R, 0, R.n, sm);
-  if (W > 0.0) set_rounds<V, NW>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kmax0, keys, q, fy, sm);
+  if (W > 0.0) set_rounds<V, NW, kPf>(A, R, (double)R.m * (log((double)R.m) + A.c0) / W, 0.0, kmax0, keys, q, fy, sm);
   PMH_TOC(sm, kStCycSet, t_set);
   epilogue<NW, kBbit>(A, R, set, keys, sm);
 }
@@ -1288,7 +1290,7 @@ __device__ void process_set(const HashArgs& A, uint64_t set, uint64_t* keys, Cha
 // set), merges its keys into the set's merge row with a 64-bit atomic min and
 // lowers the set's smallest threshold.  Finishing the set is left to
 // k_big_finish, after the kernel boundary has made every merge visible.
-template <int V, int NW>
+template <int V, int NW, bool kPf = false>
 __device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uint32_t chunk, uint64_t* keys,
                               ChainEntry* q, uint32_t qcap, uint16_t* fy, const LogCell* lt, Shared& sm) {
   constexpr int BS = NW * 64;
@@ -1305,7 +1307,7 @@ __device__ void process_chunk(const HashArgs& A, uint64_t set, uint32_t big, uin
     const double T = (double)m * (log((double)m) + A.c0 + A.c0_split) / West;
     R.T = T > 0.0 ? T : __longlong_as_double(0x7FF0000000000000ll);
     R.Tprev = 0.0;
-    round_pass<V, NW>(A, R, p0, p1, kEmptyKey, keys, q, fy, sm);
+    round_pass<V, NW, kPf>(A, R, p0, p1, kEmptyKey, keys, q, fy, sm);
     for (uint32_t k = tid; k < m; k += BS)
       if (keys[k] != kEmptyKey) atomicMin((unsigned long long*)&gk[k], (unsigned long long)keys[k]);
     if (tid == 0) atomicMin((unsigned long long*)&A.big_state[big], (unsigned long long)__double_as_longlong(R.T));
@@ -1380,7 +1382,7 @@ __device__ __forceinline__ void carve(const HashArgs& A, LogCell*& lt, uint64_t*
 // Persistent grid.  Work items: first the chunks of the split sets (heavy
 // first), then one item per remaining set.  meta = {split sets, chunk items,
 // total items}, written by k_order.
-template <int V, int NW, bool kBbit = false>
+template <int V, int NW, bool kBbit = false, bool kPf = false>
 __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
   __shared__ Shared sm;
   __shared__ uint32_t job[3];
@@ -1412,8 +1414,8 @@ __global__ __launch_bounds__(NW * 64) void k_hash_persistent(HashArgs A) {
     const uint32_t v = job[0], j1 = job[1], j2 = job[2];
     __syncthreads();
     if (v >= total) break;
-    if (v < vbig) process_chunk<V, NW>(A, A.order[j1], j1, j2, keys, q, qcap, fy, lt, sm);
-    else process_set<V, NW, kBbit>(A, A.order[j1], keys, q, qcap, fy, lt, sm);
+    if (v < vbig) process_chunk<V, NW, kPf>(A, A.order[j1], j1, j2, keys, q, qcap, fy, lt, sm);
+    else process_set<V, NW, kBbit, kPf>(A, A.order[j1], keys, q, qcap, fy, lt, sm);
   }
 }
 
@@ -2002,10 +2004,24 @@ static bool shape_ok(const HashArgs& a, size_t lds) {
   return a.qcap >= batch_size(NW) && lds >= lds_bytes_q(V, a.m, NW, a.qcap);
 }
 // Launches with an out_bbit output take the instantiations with the b-bit
-// epilogue.
+// epilogue.  Four-wave ProbMinHash3 launches whose LDS already holds a CU to
+// at most three workgroups (m above about 3,000) take the instantiation that
+// prefetches each batch's weights and ids: its 148 VGPRs allow three as well
+// (skewed batch at m = 4096: 8.70 -> 7.55 ms; 100 sets of 10^6 elements 1.65
+// -> 1.37 ms), while with four workgroups per CU they cost one.
+constexpr size_t kLdsPerCu = 160 * 1024;
 template <int V, int NW>
 static hipError_t launch_hash_t(const HashArgs& a, int grid, size_t lds, hipStream_t s) {
   if (!shape_ok<V, NW>(a, lds)) return hipErrorInvalidValue;
+  if constexpr (V == 3 && NW == 4) {
+    if ((lds + lds_static_bytes()) * 4 > kLdsPerCu) {
+      if (a.out_bbit)
+        hipLaunchKernelGGL((k_hash_persistent<V, NW, true, true>), dim3(grid), dim3(NW * 64), lds, s, a);
+      else
+        hipLaunchKernelGGL((k_hash_persistent<V, NW, false, true>), dim3(grid), dim3(NW * 64), lds, s, a);
+      return hipGetLastError();
+    }
+  }
   if (a.out_bbit)
     hipLaunchKernelGGL((k_hash_persistent<V, NW, true>), dim3(grid), dim3(NW * 64), lds, s, a);
   else
