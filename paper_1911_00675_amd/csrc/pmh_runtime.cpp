@@ -252,6 +252,12 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   // 32, with a per-batch choice above 16 in its ordered lane mode (mixed
   // batch 15.6 -> 15.3 ms, unit weights 12.2 -> 10.5 ms against 16).
   if (variant == 2 || variant == 4) c->tune.chain_expect = variant == 4 ? 32.0 : 16.0;
+  // A split set's chunk fills its own m keys (about m (ln m + c0_split)
+  // points), so larger m takes larger chunks: sets of >= 2^16 elements in
+  // chunks of 2^15 above m = 2048 (skewed batch at m = 4096: ProbMinHash1
+  // 9.55 -> 9.36 ms, ProbMinHash3 7.55 -> 7.37, ProbMinHash4 9.75 -> 9.47;
+  // no change at m = 1024).
+  if (m > 2048) c->tune.split_log2 = 16;
   c->device = dev;
   c->lds_limit = lim;
   hipDeviceProp_t prop;

@@ -88,7 +88,7 @@ def test_fused_epilogue_bit_exact(pmh, variant):
     split), and the separate pack kernel's words."""
     from paper_1911_00675_amd import workloads as W
     rng = np.random.default_rng(900 + variant)
-    sizes = [0, 1, 3, 80, 40000, 0, 700, 5]
+    sizes = [0, 1, 3, 80, 70000, 0, 700, 5]  # split at every m here (2^15 up to m = 2048, 2^16 above)
     n = sum(sizes)
     b_ = W.Batch(rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64), rng.exponential(size=n) + 1e-3,
                  np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64))

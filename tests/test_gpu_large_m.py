@@ -30,7 +30,7 @@ def _dev(a):
 
 def _batch(seed):
     rng = np.random.default_rng(seed)
-    sizes = [0, 1, 2, 7, 300, 2500, 40000, 13, 0, 90]
+    sizes = [0, 1, 2, 7, 300, 2500, 70000, 13, 0, 90]  # 70,000 >= 2^16: split at these m
     n = sum(sizes)
     ids = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64)
     w = rng.pareto(1.5, size=n) + 0.05

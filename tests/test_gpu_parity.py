@@ -301,12 +301,13 @@ def test_split_sets(pmh, variant, m):
 def test_large_m_four_waves(pmh, variant):
     """m = 4096, where contexts default to 4 waves per workgroup (8 for
     ProbMinHash2/4): ragged sets
-    up to 40,000 elements (split ones included) in the batched and graph
+    up to 70,000 elements (split ones included: above m = 2048 sets of
+    >= 2^16 elements split) in the batched and graph
     forms, and the same keys with 1 and 2 waves."""
     print(f"m=4096 PMH{variant}", flush=True)
     m = 4096
     rng = np.random.default_rng(70 + variant)
-    sizes = [0, 1, 3, 50, 700, 4096, 9000, 40000, 12, 2]
+    sizes = [0, 1, 3, 50, 700, 4096, 9000, 70000, 12, 2]
     ids = rng.integers(0, 2**64 - 1, size=sum(sizes), dtype=np.uint64)
     w = rng.uniform(size=sum(sizes)) + 1e-3
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
