@@ -74,20 +74,27 @@ enum {
   PMH_ERR_NO_ENTRY = 11       /* pmh_tuning_load: no stored tuning for this device, m and variant */
 };
 
-/* Tunables of the per-set schedule.  None of them changes any result. */
+/* Tunables of the per-set schedule.  None of them changes any result.
+ * pmh_init sets defaults per variant and m (pmh_get_tuning reads them). */
 typedef struct {
-  double c0;          /* first value threshold T0 = m (ln m + c0) / sum(w) */
+  double c0;          /* first value threshold T0 = m (ln m + c0) / sum(w) (default 3; 2 for
+                         ProbMinHash3) */
   double grow;        /* threshold growth per extra round (> 1) */
   int max_rounds;     /* rounds before the unbounded final round (>= 1) */
-  double chain_expect;/* elements expecting more points go to wave-chain mode */
-  int lane_budget;    /* lane-mode points before an element moves to chain mode */
+  double chain_expect;/* elements expecting more points go to wave-chain mode (default 48;
+                         ProbMinHash2 16; ProbMinHash4 32, keeping streams of 16-32 points in
+                         lane mode only where a batch holds a wave of them) */
+  int lane_budget;    /* ProbMinHash1/3: lane-mode points before an element moves on */
   int waves;          /* wavefronts per workgroup: 1, 2, 4, or 8 for ProbMinHash2/4 (default 2;
-                         4 for m > 1536; fewer where the LDS does not fit) */
+                         above m = 1536 4 for ProbMinHash1/3; above m = 3072 8 for
+                         ProbMinHash2/4, 4 where eight do not fit; fewer where the LDS does
+                         not fit) */
   int kmax_refresh;   /* element batches between stop-limit refreshes (>= 1) */
   int blocks_per_cu;  /* persistent grid = CUs * this (0: occupancy limit) */
   double mini_expect; /* ProbMinHash1/3 elements expecting more points run as 4-lane mini-chains */
   int split_log2;     /* batched forms: sets of >= 2^split_log2 elements are split into chunks of
-                         2^(split_log2-1) elements on separate workgroups (0: never; else 2..21).
+                         2^(split_log2-1) elements on separate workgroups (0: never; else 2..21;
+                         default 15, 16 above m = 2048).
                          Needs out_keys, out_val or out_id, whose rows hold the merged keys. */
   double c0_split;    /* extra margin added to c0 in the chunks' threshold */
 } pmh_tuning;
