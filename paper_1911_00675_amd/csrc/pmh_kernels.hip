@@ -961,12 +961,14 @@ __device__ double block_weight_sum(const HashArgs& A, const Round& R, uint32_t p
 
 // ProbMinHash4 lane mode over one batch: streams expecting more than
 // chain_expect points go to the chain queue, the others run one per lane.  In
-// sets whose elements expect more than a point each (R.sort) they are first
-// counted into classes by expected points and dealt to the lanes longest
-// first through LDS (weights and ids then read again, from cache), so the 64
-// lanes of a wave get streams of similar length: a wave runs as many steps as
-// its longest stream.  Otherwise each thread keeps its own prefetched ones.
-// (`sort` is block-uniform.)
+// sets whose elements expect more than a point each (`sort`, block-uniform)
+// they are first counted into classes by expected points and dealt to the
+// lanes longest first through LDS (weights and ids then read again, from
+// cache), so the 64 lanes of a wave get streams of similar length: a wave
+// runs as many steps as its longest stream; streams expecting more than
+// kLaneSure points stay only if the batch holds a wave of them.  Otherwise
+// each thread keeps its own prefetched ones, and streams expecting more than
+// kLaneSure points go to the chain queue.
 template <int V, int NW>
 __device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, uint32_t base, uint32_t p1,
                                            const double* wc, const uint64_t* idc, double Teff, uint64_t kmax,
