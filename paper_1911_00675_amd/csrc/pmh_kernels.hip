@@ -392,7 +392,9 @@ __device__ __forceinline__ void lds_min(uint64_t* keys, uint32_t l, uint64_t key
 struct ChainEntry {
   uint32_t p;
   uint32_t i;     // next point index
-  uint64_t tacc;  // ProbMinHash1/2 fixed-point accumulator through point i-1
+  uint64_t tacc;  // ProbMinHash1/2 fixed-point accumulator through point i-1;
+                  // ProbMinHash3: the element key K (no accumulator), so a
+                  // refill needs neither the id nor its hash
 };
 
 struct Shared {
@@ -524,7 +526,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       if (!(lb < R.T)) return step;
       if (make_key(lb, p) >= kmax) return step;
       if (step == budget) {
-        push_mini(sm, q, R.qcap, p, i, 0);
+        push_mini(sm, q, R.qcap, p, i, K);
         return step;
       }
       const uint64_t w0 = mix64(pb);
@@ -821,9 +823,9 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
         const ChainEntry ce = q[R.qcap - 1 - e];
         p = ce.p;
         i0 = ce.i;
-        tacc = ce.tacc;
+        tacc = V == 3 ? 0 : ce.tacc;
         winv = 1.0 / elem_w(R, p);
-        K = mix64(R.ids[p] ^ R.K0);
+        K = V == 3 ? ce.tacc : mix64(R.ids[p] ^ R.K0);
         pb = pbase(K, i0) + (uint64_t)j * kPointStep;
         have = true;
         if (j == 0) PMH_STAT(sm, kStMiniElems, 1);
@@ -895,7 +897,8 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
     e = (uint32_t)__shfl((int)e, 0);
     if (e >= qtail) break;
     const ChainEntry ce = q[e];
-    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), mix64(R.ids[ce.p] ^ R.K0), keys, g, fs, sm);
+    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), V == 3 ? ce.tacc : mix64(R.ids[ce.p] ^ R.K0), keys, g, fs,
+                  sm);
   }
   PMH_TOC(sm, kStCycChain, t_chain);
   PMH_TIC(t_mini);
@@ -1138,16 +1141,17 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
       const uint32_t i0 = first_index<V>(w, R.Tprev, R.imax);
       if (i0 > R.imax) continue;
       const double lam = w * (V == 3 ? Teff - R.Tprev : Teff);  // expected points generated
+      // ProbMinHash3 queue entries carry K (see ChainEntry)
+      const uint64_t K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
       if (lam > A.chain_expect) {
-        push_long(sm, q, p, i0, 0);
+        push_long(sm, q, p, i0, V == 3 ? K : 0);
         continue;
       }
       if ((V == 1 || V == 3) && lam > A.mini_expect) {
-        push_mini(sm, q, qcap, p, i0, 0);
+        push_mini(sm, q, qcap, p, i0, V == 3 ? K : 0);
         continue;
       }
       const double winv = 1.0 / w;
-      const uint64_t K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
       const int steps = lane_elem<V, NW>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget, i0);
 #ifdef PMH_STATS
       // wave-level cost of this element slot: the longest lane
