@@ -392,9 +392,10 @@ __device__ __forceinline__ void lds_min(uint64_t* keys, uint32_t l, uint64_t key
 struct ChainEntry {
   uint32_t p;
   uint32_t i;     // next point index
-  uint64_t tacc;  // ProbMinHash1/2 fixed-point accumulator through point i-1;
-                  // ProbMinHash3: the element key K (no accumulator), so a
-                  // refill needs neither the id nor its hash
+  uint64_t tacc;  // ProbMinHash1: fixed-point accumulator through point i-1;
+                  // ProbMinHash2/3/4 (no accumulator carried: 2/4 restart at
+                  // point 1): the element key K, so a refill needs neither
+                  // the id nor its hash
 };
 
 struct Shared {
@@ -595,7 +596,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       if (x >= R.Tprev && key < kmax) lds_min(keys, l, key);
       if (i == m) return (int)step + 1;
     }
-    push_long(sm, q, p, 1, 0);
+    push_long(sm, q, p, 1, K);
     return (int)kSteps;
   }
 }
@@ -897,7 +898,7 @@ __device__ void chain_pass(const HashArgs& A, const Round& R, uint64_t* keys, Ch
     e = (uint32_t)__shfl((int)e, 0);
     if (e >= qtail) break;
     const ChainEntry ce = q[e];
-    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), V == 3 ? ce.tacc : mix64(R.ids[ce.p] ^ R.K0), keys, g, fs,
+    chain_elem<V>(A, R, ce, 1.0 / elem_w(R, ce.p), V != 1 ? ce.tacc : mix64(R.ids[ce.p] ^ R.K0), keys, g, fs,
                   sm);
   }
   PMH_TOC(sm, kStCycChain, t_chain);
@@ -994,7 +995,7 @@ __device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, ui
     PMH_STAT(sm, kStElems, 1);
     const double lam = w * Teff;  // expected points generated
     if (lam > A.chain_expect || (!sort && lam > (double)kLaneSure)) {
-      push_long(sm, q, pk[k], 1, 0);
+      push_long(sm, q, pk[k], 1, mix64(idc[k] ^ R.K0));
       continue;
     }
     cls[k] = lam < (double)(kSortClasses - 1) ? (int)lam : kSortClasses - 1;
@@ -1025,7 +1026,7 @@ __device__ __forceinline__ void lane_batch(const HashArgs& A, const Round& R, ui
       if (cls[k] < 0) continue;
       const uint32_t o = off[cls[k]];
       if (o == kNoLane) {
-        push_long(sm, q, base + k * BS + tid, 1, 0);
+        push_long(sm, q, base + k * BS + tid, 1, mix64(idc[k] ^ R.K0));
         cls[k] = -1;
       } else {
         idx[o + pos[k]] = (uint16_t)(k * BS + tid);
@@ -1141,16 +1142,18 @@ __device__ uint64_t round_pass(const HashArgs& A, const Round& R, uint32_t p0, u
       const uint32_t i0 = first_index<V>(w, R.Tprev, R.imax);
       if (i0 > R.imax) continue;
       const double lam = w * (V == 3 ? Teff - R.Tprev : Teff);  // expected points generated
-      // ProbMinHash3 queue entries carry K (see ChainEntry)
-      const uint64_t K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
+      // ProbMinHash2/3 queue entries carry K (see ChainEntry)
+      uint64_t K = 0;
+      if constexpr (V != 1) K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
       if (lam > A.chain_expect) {
-        push_long(sm, q, p, i0, V == 3 ? K : 0);
+        push_long(sm, q, p, i0, K);
         continue;
       }
       if ((V == 1 || V == 3) && lam > A.mini_expect) {
-        push_mini(sm, q, qcap, p, i0, V == 3 ? K : 0);
+        push_mini(sm, q, qcap, p, i0, K);
         continue;
       }
+      if constexpr (V == 1) K = mix64((kPrefetch ? idc[k] : R.ids[p]) ^ R.K0);
       const double winv = 1.0 / w;
       const int steps = lane_elem<V, NW>(A, R, p, winv, K, kmax, keys, sm, q, A.lane_budget, i0);
 #ifdef PMH_STATS
