@@ -213,8 +213,10 @@ def points_summary(out_path):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    # the first launches of a process run a few percent slower (clocks still
+    # ramping): ten untimed steps (about 0.1 s) reach the steady state
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sets", type=int, default=100_000)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
