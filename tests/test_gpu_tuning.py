@@ -55,3 +55,17 @@ def test_autotune_cache(pmh, tmp_path):
     again = pmh.Context(SEED, 128, 3)
     assert again.autotune(*d, trials=1, cache=path) == best
     assert again.get_tuning().as_dict() == best
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4])
+def test_default_tuning(pmh, variant):
+    """pmh_init's defaults per variant and m (documented in pmh.h): thresholds,
+    waves per workgroup, chain threshold and split threshold."""
+    for m, waves in ((256, 2), (1024, 2), (2048, (4, 2, 4, 2)[variant - 1]), (4096, (4, 8, 4, 8)[variant - 1]),
+                     (8192, 4)):
+        t = pmh.Context(SEED, m, variant).get_tuning().as_dict()
+        assert t["waves"] == waves, (m, t)
+        assert t["c0"] == (2.0 if variant == 3 else 3.0)
+        assert t["grow"] == (1.35 if variant == 3 else 2.0)
+        assert t["chain_expect"] == {1: 48.0, 2: 16.0, 3: 48.0, 4: 32.0}[variant]
+        assert t["split_log2"] == (16 if m > 2048 else 15)
