@@ -36,6 +36,11 @@ struct Tables {
   uint32_t te_rounds;
   uint32_t redraws;
   uint32_t lemire_floor;
+  // scal[0..2] and scal[4] by value, read back once the tables are built:
+  // kernels take them from their arguments (scalar constant loads), not
+  // through the pointer, which a call in a loop would force them to reload.
+  double te_lam, te_a, te_c1;  // ProbMinHash3's truncated-exponential lambda, a, c1
+  double delta;                // ProbMinHash4's last-point scale
 };
 constexpr uint32_t kTeRoundsMax = 32;  // word slots 16..79
 constexpr uint32_t kRedrawsMax = 8;    // word slots 1..8

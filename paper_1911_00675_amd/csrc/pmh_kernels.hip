@@ -519,7 +519,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
       ++i;
     }
   } else if constexpr (V == 3) {
-    const double lam = t.scal[0], a3 = t.scal[1], c13 = t.scal[2];
+    const double lam = t.te_lam, a3 = t.te_a, c13 = t.te_c1;
     uint32_t i = i0;
     uint64_t pb = pbase(K, i0);
     for (int step = 0;; ++step, pb += kPointStep) {
@@ -578,7 +578,7 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
           x = winv * (gp + L[kLaneTab + i] * trunc_exp(w0, pb, L[2 * kLaneTab + i], L[3 * kLaneTab + i],
                                                        L[4 * kLaneTab + i], t));
         } else {
-          x = winv * (gp + t.scal[4] * exp1<false>(w0, lt));
+          x = winv * (gp + t.delta * exp1<false>(w0, lt));
         }
       }
       PMH_STAT(sm, kStLanePts, 1);
@@ -674,7 +674,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t);
+        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.te_lam, t.te_a, t.te_c1, t);
         key = make_key(x, p);
       }
     } else {
@@ -693,7 +693,7 @@ __device__ void chain_elem(const HashArgs& A, const Round& R, ChainEntry e, doub
           if (!(e < 1.0)) e = te_slow(pb, t.lam[i], t.a[i], c1v, t.te_rounds, t.expm1c);
           x = winv * (gp + dg * e);
         } else {
-          x = winv * (gp + t.scal[4] * exp1<false>(w0, lt));
+          x = winv * (gp + t.delta * exp1<false>(w0, lt));
         }
         key = make_key(x, p);
       }
@@ -849,7 +849,7 @@ __device__ void mini_pass(const HashArgs& A, const Round& R, uint64_t* keys, Cha
       const double lb = winv * (double)(i - 1);
       stop = !valid || !(lb < R.T) || make_key(lb, p) >= kmax;
       if (!stop) {
-        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.scal[0], t.scal[1], t.scal[2], t);
+        x = A.binary ? lb + u32v(w0) : lb + winv * trunc_exp(w0, pb, t.te_lam, t.te_a, t.te_c1, t);
         key = make_key(x, p);
       }
     }

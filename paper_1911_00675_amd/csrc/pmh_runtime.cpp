@@ -298,6 +298,14 @@ int pmh_init(uint64_t seed, uint32_t m, int variant, pmh_ctx** out) {
   if (!rc && scratch_work(dev, &c->scratch, &c->scratch_cap) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && launch_init_tables(variant, m, c->t, nullptr) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (!rc && hipDeviceSynchronize() != hipSuccess) rc = PMH_ERR_DEVICE;
+  double sc[8];
+  if (!rc && hipMemcpy(sc, c->t.scal, sizeof(sc), hipMemcpyDeviceToHost) != hipSuccess) rc = PMH_ERR_DEVICE;
+  if (!rc) {
+    c->t.te_lam = sc[0];
+    c->t.te_a = sc[1];
+    c->t.te_c1 = sc[2];
+    c->t.delta = sc[4];
+  }
   if (!rc && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) rc = PMH_ERR_DEVICE;
   if (rc) {
     pmh_destroy(c);
