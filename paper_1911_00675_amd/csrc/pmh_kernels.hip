@@ -384,8 +384,11 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int src) {
 __device__ __forceinline__ uint64_t lds_load_u64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// The atomic returns nothing, so the wave does not wait on it; reading the
+// slot first to skip atomics that cannot lower it put that read's latency
+// on every point.
 __device__ __forceinline__ void lds_min(uint64_t* keys, uint32_t l, uint64_t key) {
-  if (key < lds_load_u64(&keys[l])) atomicMin((unsigned long long*)&keys[l], (unsigned long long)key);
+  atomicMin((unsigned long long*)&keys[l], (unsigned long long)key);
 }
 
 // ---------------------------------------------------------------- set state
