@@ -558,6 +558,16 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
                                                       lane_tab_offset(fy_waves(NW), m, kEpt * NW * 64));
     uint32_t tr[kSteps];
     uint64_t tacc = 0;
+    // ProbMinHash4's rolled loop loads the next step's gamma_{i-1},
+    // gamma_i - gamma_{i-1} and c1_i one step ahead (index clamped to the
+    // slice): at two waves per SIMD the LDS latency was exposed every step.
+    constexpr bool kAhead = V == 4 && kFyLaneRolled<V, NW>;
+    double gp_n = 0.0, dg_n = 0.0, c1_n = 0.0;
+    if constexpr (kAhead) {
+      gp_n = L[0];
+      dg_n = L[kLaneTab + 1];
+      c1_n = L[4 * kLaneTab + 1];
+    }
 #pragma unroll kUnroll
     for (uint32_t step = 0; step < kSteps; ++step) {
       const uint32_t i = step + 1;
@@ -571,15 +581,27 @@ __device__ __forceinline__ int lane_elem(const HashArgs& A, const Round& R, uint
         if (!(x < R.T)) return (int)step + 1;
         if (make_key(x, p) >= kmax) return (int)step + 1;
       } else {
-        const double gp = L[i - 1];  // gamma_{i-1}
+        double gp, dg, c1v;  // gamma_{i-1}, gamma_i - gamma_{i-1}, c1_i
+        if constexpr (kAhead) {
+          gp = gp_n;
+          dg = dg_n;
+          c1v = c1_n;
+          const uint32_t in = i < kSteps ? i + 1u : i;
+          gp_n = L[in - 1];
+          dg_n = L[kLaneTab + in];
+          c1_n = L[4 * kLaneTab + in];
+        } else {
+          gp = L[i - 1];
+          dg = L[kLaneTab + i];
+          c1v = L[4 * kLaneTab + i];
+        }
         const double lb = A.binary ? (double)(i - 1) : winv * gp;
         if (!(lb < R.T)) return (int)step;
         if (make_key(lb, p) >= kmax) return (int)step;
         if (A.binary) {
           x = lb + u32v(w0);
         } else if (i < m) {
-          x = winv * (gp + L[kLaneTab + i] * trunc_exp(w0, pb, L[2 * kLaneTab + i], L[3 * kLaneTab + i],
-                                                       L[4 * kLaneTab + i], t));
+          x = winv * (gp + dg * trunc_exp(w0, pb, L[2 * kLaneTab + i], L[3 * kLaneTab + i], c1v, t));
         } else {
           x = winv * (gp + t.delta * exp1<false>(w0, lt));
         }
