@@ -226,6 +226,8 @@ def parse():
     ap.add_argument("--no-binary", action="store_true")
     ap.add_argument("--no-update", action="store_true")
     ap.add_argument("--no-skewed", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuned timings of the skewed batch (profiled runs)")
     ap.add_argument("--no-small", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=200_000, help="measured requests (after 20,000 warm-up)")
@@ -667,7 +669,7 @@ def main():
                                                             "per_point": OPS_PER_POINT[v]},
                                               "hbm_frac": (16.0 * sb.num_elements + 12.0 * sb.num_sets * 4096)
                                               / (kms * 1e-3) / PEAK_HBM}}
-            if v in (2, 4):
+            if v in (2, 4) and not args.no_autotune:
                 default = sc.get_tuning().as_dict()
                 sc.autotune(sids, sw, soff, trials=2)
                 tuned = sc.get_tuning().as_dict()
