@@ -54,3 +54,12 @@ def test_committed_record_is_complete(variant):
     assert k["fetch_kib"] > 0 and k["write_kib"] > 0
     assert rec["calibration"]["fetch_factor"] > 0 and rec["calibration"]["write_factor"] > 0
     assert rec["num_sets"] == 100_000
+
+
+def test_profiled_runs_can_skip_the_autotuner(monkeypatch):
+    """Profiled skewed-batch runs pass --no-autotune, so their kernel traces hold
+    only default-tuning launches; the plain bench keeps the autotuned leg."""
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-autotune"])
+    assert bench.parse().no_autotune
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    assert not bench.parse().no_autotune
